@@ -1,0 +1,28 @@
+"""Build the oracle's C part (test infrastructure only).
+
+Compiles ``oracle/matmul_ref.c`` with gcc into ``oracle/liboracle.so``.  The
+checker is built here so tests can run; the product library never links it.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "matmul_ref.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build_oracle(force: bool = False) -> str:
+    """Compile the oracle shared library; return its path."""
+    if (not force and os.path.exists(LIB)
+            and os.path.getmtime(LIB) >= os.path.getmtime(SRC)):
+        return LIB
+    tmp = LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+           "-Wall", "-Wextra", "-o", tmp, SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build_oracle(force=True))
