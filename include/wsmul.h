@@ -1,0 +1,217 @@
+/*
+ * wsmul.h -- exact Strassen-Winograd matrix products over Z/pZ on MI355X,
+ * run under the memory schedules of Boyer, Dumas, Pernet and Zhou,
+ * "Memory efficient scheduling of Strassen-Winograd's matrix multiplication
+ * algorithm" (ISSAC 2009).
+ *
+ * One operation sits behind this header (Section 3.2):
+ *
+ *     C <- (alpha * A * B + beta * C) mod p
+ *
+ * with A m x k, B k x n, C m x n, every entry a canonical residue in [0, p).
+ * Winograd's 2x2 recursion (Section 2: 8 pre-additions, 7 products,
+ * 7 post-additions) is applied `levels` times; below that the base case is a
+ * classical product on the GPU's matrix cores.  The schedule selects where
+ * every intermediate block lives (the "loc." column of the paper's tables).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * - Matrices are HIP device pointers, row-major, with leading dimensions
+ *   lda >= k, ldb >= n, ldc >= n (in elements).  Storage is binary64 holding
+ *   integers (WS_F64) or int64 (WS_I64).  The caller owns A, B, C and any
+ *   workspace it attaches; the library frees none of them.
+ * - Execution is asynchronous on the stream given in ws_args (or the one set
+ *   with wsmul_set_stream; NULL means the null stream).  A return of WS_OK
+ *   means the work was enqueued.
+ * - Errors are status codes; nothing is thrown across this boundary.  All
+ *   argument checks run before any launch, so WS_EINVAL, WS_ESHAPE,
+ *   WS_EMODULUS and WS_ESCHEDULE leave A, B and C untouched.  After WS_EHIP
+ *   the contents of C (and of A, B for overwriting schedules) are
+ *   unspecified.  wsmul_last_error() returns a thread-local message.
+ * - Read-only schedules leave A and B bitwise unchanged.  WS_OVERWRITE (and
+ *   the sub-schedules that overwrite) leave A and/or B in a state that is a
+ *   fixed function of the inputs and the schedule's tables.
+ * - Calls on one stream are ordered; two concurrent calls on different
+ *   streams must not share a workspace.
+ */
+#ifndef WSMUL_H
+#define WSMUL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define WSMUL_API __attribute__((visibility("default")))
+#else
+#define WSMUL_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WS_OK = 0,
+    WS_EINVAL = 1,     /* bad pointer, negative size, bad leading dimension */
+    WS_ESHAPE = 2,     /* shape not supported by the chosen schedule       */
+    WS_EMODULUS = 3,   /* p outside [2, 2^24) or beyond the base's bound   */
+    WS_ERANGE = 4,     /* WS_FLAG_CHECK: an entry outside [0, p)           */
+    WS_ESCHEDULE = 5,  /* unknown schedule, or beta != 0 where not allowed */
+    WS_ENOMEM = 6,     /* attached workspace too small / allocation failed */
+    WS_EHIP = 7        /* a HIP runtime call failed                        */
+} ws_status;
+
+typedef enum {
+    WS_CLASSICAL = 0,        /* no Winograd level: one base product (comparator)    */
+    WS_TWO_TEMP = 1,         /* beta == 0: Table 1; beta != 0: Table 9 (square)    */
+    WS_OVERWRITE = 2,        /* beta == 0: Table 3; beta != 0: Table 6; destroys A, B */
+    WS_READONLY_INPLACE = 3, /* Algorithm 2; beta must be 0; no temporary at all   */
+    WS_HL_THREE_TEMP = 4,    /* Table 2 (three temporaries, any beta)              */
+    WS_AUTO = 5,             /* schedule, depth and base chosen by the autotuner   */
+    WS_OVR = 6,              /* Table 5: C = A*B, one temporary, destroys B        */
+    WS_ACCR = 7              /* Table 7: two temporaries, destroys B (square)      */
+} ws_schedule;
+
+typedef enum { WS_F64 = 0, WS_I64 = 1 } ws_dtype;
+
+typedef enum {
+    WS_BASE_AUTO = 0,        /* library choice                                      */
+    WS_BASE_F64_MFMA = 1,    /* binary64 matrix cores, delayed modular reduction    */
+    WS_BASE_I8_LIMBS = 2     /* centred residues as signed 8-bit digits, int32 sums */
+} ws_base;
+
+enum {
+    WS_FLAG_CHECK = 1u << 0,   /* verify every entry lies in [0, p) first (WS_ERANGE) */
+    WS_FLAG_NOFUSE = 1u << 1,  /* one launch per schedule row (no row fusion)         */
+    WS_FLAG_TRACE = 1u << 2    /* time every launch with events (wsmul_get_trace)     */
+};
+
+/* Full argument block.  Zero lda/ldb/ldc mean dense (k, n, n). */
+typedef struct ws_args {
+    int64_t m, k, n, p;
+    int64_t lda, ldb, ldc;
+    int64_t alpha, beta;       /* any int64; reduced mod p                          */
+    void *A, *B, *C;
+    int32_t dtype;             /* ws_dtype                                           */
+    int32_t schedule;          /* ws_schedule                                        */
+    int32_t levels;            /* Winograd depth >= 0; -1 lets the autotuner choose  */
+    int32_t base;              /* ws_base                                            */
+    void *workspace;           /* NULL: use the attached one or allocate (stream-ordered) */
+    uint64_t workspace_bytes;
+    void *stream;              /* hipStream_t; NULL: the stream from wsmul_set_stream */
+    uint32_t flags;
+    uint32_t reserved;
+} ws_args;
+
+/* Counters of the most recent call on this thread. */
+typedef struct ws_stats {
+    uint64_t workspace_bytes;      /* temporaries of the schedule (its extra memory)   */
+    uint64_t peak_temp_bytes;      /* high-water mark of temporaries since reset       */
+    uint64_t internal_alloc_bytes; /* bytes the library allocated itself for the call  */
+    uint64_t add_launches;         /* fused addition launches                         */
+    uint64_t gemm_launches;        /* base-product launches                           */
+    uint64_t element_additions;    /* schedule addition rows x block elements          */
+    uint64_t base_flops;           /* sum of 2*M*N*K over base products               */
+    uint64_t rows;                 /* schedule rows before fusion                     */
+    uint64_t levels;               /* Winograd depth actually used                    */
+    int64_t schedule;              /* table actually run (see wsmul_schedule_name)    */
+    int64_t base;                  /* base kind actually used                         */
+} ws_stats;
+
+/*
+ * The spec call: binary64 storage, dense leading dimensions, default
+ * stream and workspace.  C <- (alpha*A*B + beta*C) mod p with `levels`
+ * Winograd levels under `schedule` (Section 3.2; schedules of Tables 1-9 and
+ * Algorithm 2).
+ */
+WSMUL_API int wsmul_mod_p(int64_t m, int64_t k, int64_t n, int64_t p,
+                void *A, void *B, void *C, int64_t alpha, int64_t beta,
+                int schedule, int levels);
+
+/* The same with int64 storage. */
+WSMUL_API int wsmul_mod_p_i64(int64_t m, int64_t k, int64_t n, int64_t p,
+                    void *A, void *B, void *C, int64_t alpha, int64_t beta,
+                    int schedule, int levels);
+
+/* Everything explicit (leading dimensions, dtype, base, stream, workspace). */
+WSMUL_API int wsmul_mod_p_ex(const ws_args *args);
+
+/*
+ * Bytes of temporaries the schedule needs (its "extra memory": Eq. (1) for
+ * Table 1, Eq. (2) for Table 2, the bounds of Sections 5-6 for Tables 5-9,
+ * zero for Table 3 and Algorithm 2), for dense binary64 or int64 storage.
+ * Returns 0 for unsupported combinations (check wsmul_last_error()).
+ */
+WSMUL_API size_t wsmul_workspace_bytes(int64_t m, int64_t k, int64_t n, int dtype, int schedule,
+                             int levels, int beta_nonzero);
+
+/* Attach a caller-owned device workspace used when ws_args.workspace is NULL
+ * (NULL/0 detaches).  The library never frees it. */
+WSMUL_API int wsmul_set_workspace(void *ptr, size_t bytes);
+
+/* Default stream for calls whose ws_args.stream is NULL. */
+WSMUL_API int wsmul_set_stream(void *stream);
+
+/* Kernel time per class, summed over calls made with WS_FLAG_TRACE since the
+ * last wsmul_reset_stats (events recorded on the call's stream around every
+ * launch; a traced call waits for its own completion). */
+typedef struct ws_trace {
+    uint64_t add_launches, gemm_launches;
+    double add_ms, gemm_ms;
+    double add_bytes;          /* algorithmic bytes of the addition launches: 8*(nin+nout)*elements */
+    double gemm_flops;         /* 2*M*N*K of the base products */
+} ws_trace;
+
+WSMUL_API int wsmul_get_stats(ws_stats *out);
+WSMUL_API int wsmul_get_trace(ws_trace *out);
+WSMUL_API int wsmul_reset_stats(void);
+WSMUL_API const char *wsmul_last_error(void);
+WSMUL_API const char *wsmul_schedule_name(int table_id);
+WSMUL_API const char *wsmul_version(void);
+
+/* ------------------------------------------------------------------------
+ * Plan introspection (host only, no GPU needed).
+ *
+ * A plan is the schedule expanded to `levels`: a list of operations on views
+ * of A, B, C and the workspace.  Consecutive addition rows of a table are
+ * fused into one operation when every view has the same shape and distinct
+ * views do not overlap; addition rows right after a base product become its
+ * epilogue under the same rule (plus: no epilogue output may overlap the
+ * product's operands).
+ */
+#define WS_MAX_IN 8
+#define WS_MAX_OUT 6
+
+enum { WS_BUF_A = 0, WS_BUF_B = 1, WS_BUF_C = 2, WS_BUF_W = 3 };
+enum { WS_OP_ADD = 0, WS_OP_GEMM = 1 };
+
+typedef struct ws_view {
+    int32_t buf;               /* WS_BUF_*                                 */
+    int32_t pad;
+    int64_t off, rows, cols, ld;  /* element offset, shape, leading dim   */
+} ws_view;
+
+/* out[o] <- sum_i coef[o][i] * in[i]  (mod p), elementwise.  For a base
+ * product, in[0] stands for alpha*a*b (already reduced) and is not read. */
+typedef struct ws_op_desc {
+    int32_t kind;              /* WS_OP_ADD or WS_OP_GEMM   */
+    int32_t nin, nout, depth;
+    int64_t alpha;
+    ws_view a, b;
+    ws_view in[WS_MAX_IN];
+    ws_view out[WS_MAX_OUT];
+    int64_t coef[WS_MAX_OUT][WS_MAX_IN];
+} ws_op_desc;
+
+/* Fill `stats` (workspace bytes, launches, counts) for args without running.
+ * Pointers in args are not dereferenced and may be NULL. */
+WSMUL_API int wsmul_plan_info(const ws_args *args, ws_stats *stats);
+
+/* Copy up to `cap` operations of the plan into `ops`; *count receives the
+ * total number (call with cap = 0 to size the buffer). */
+WSMUL_API int wsmul_plan_export(const ws_args *args, ws_op_desc *ops, int64_t cap, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WSMUL_H */

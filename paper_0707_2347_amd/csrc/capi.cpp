@@ -1,0 +1,440 @@
+// The C-ABI: argument checks, plan cache, workspace, launch loop, counters.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "wsmul.h"
+#include "wsmul_internal.hpp"
+
+using namespace wsmul;
+
+namespace {
+
+thread_local std::string g_err;
+thread_local ws_stats g_stats{};
+thread_local ws_trace g_trace{};
+
+std::mutex g_mu;
+void *g_ws = nullptr;
+size_t g_ws_bytes = 0;
+hipStream_t g_stream = nullptr;
+
+struct KeyHash {
+    size_t operator()(const PlanKey &k) const {
+        const int64_t v[] = {k.m, k.k, k.n, k.p, k.lda, k.ldb, k.ldc, k.alpha, k.beta,
+                             k.dtype, k.table, k.levels, k.fuse};
+        uint64_t h = 1469598103934665603ull;
+        for (int64_t x : v) {
+            h ^= (uint64_t)x;
+            h *= 1099511628211ull;
+        }
+        return (size_t)h;
+    }
+};
+std::unordered_map<PlanKey, std::shared_ptr<Plan>, KeyHash> g_plans;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int64_t canon(int64_t x, int64_t p) {
+    const int64_t r = x % p;
+    return r < 0 ? r + p : r;
+}
+
+}  // namespace
+
+namespace wsmul {
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+std::shared_ptr<Plan> get_plan(const PlanKey &key) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end())
+        return it->second;
+    auto plan = std::make_shared<Plan>();
+    build_plan(key, *plan);
+    if (g_plans.size() > 512)
+        g_plans.clear();
+    g_plans.emplace(key, plan);
+    return plan;
+}
+
+// Normalise and check a request.  On success fills the plan key.
+int prepare(const ws_args *in, ws_args &a, PlanKey &key, Resolved &res) {
+    if (!in)
+        return fail(WS_EINVAL, "null argument block");
+    a = *in;
+    if (a.m < 0 || a.k < 0 || a.n < 0)
+        return fail(WS_EINVAL, "negative dimension");
+    if (a.p < 2 || a.p >= (int64_t(1) << 24))
+        return fail(WS_EMODULUS, "p must lie in [2, 2^24)");
+    if (a.dtype != WS_F64 && a.dtype != WS_I64)
+        return fail(WS_EINVAL, "dtype must be WS_F64 or WS_I64");
+    if (a.lda == 0)
+        a.lda = a.k;
+    if (a.ldb == 0)
+        a.ldb = a.n;
+    if (a.ldc == 0)
+        a.ldc = a.n;
+    if (a.lda < a.k || a.ldb < a.n || a.ldc < a.n || a.lda < 0 || a.ldb < 0 || a.ldc < 0)
+        return fail(WS_EINVAL, "leading dimension smaller than the row length");
+    if ((a.m > 0 && a.k > 0 && !a.A) || (a.k > 0 && a.n > 0 && !a.B) ||
+        (a.m > 0 && a.n > 0 && !a.C))
+        return fail(WS_EINVAL, "null matrix pointer");
+    if (a.base != WS_BASE_AUTO && a.base != WS_BASE_F64_MFMA && a.base != WS_BASE_I8_LIMBS)
+        return fail(WS_EINVAL, "unknown base kind");
+    const bool beta_nz = canon(a.beta, a.p) != 0;
+    if (a.schedule == WS_AUTO || a.levels < 0) {
+        const int rc = autotune_choice(a, beta_nz);
+        if (rc != WS_OK)
+            return rc;
+    }
+    if (a.base == WS_BASE_AUTO)
+        a.base = WS_BASE_F64_MFMA;
+    if (a.base == WS_BASE_I8_LIMBS && !limbs_supported(a.p))
+        return fail(WS_EMODULUS, "p too large for three signed 8-bit digits (p <= 16711423)");
+    res = resolve_schedule(a.schedule, a.m, a.k, a.n, beta_nz, a.levels);
+    if (res.status != WS_OK)
+        return fail(res.status, res.error);
+    std::memset(&key, 0, sizeof(key));
+    key.m = a.m;
+    key.k = a.k;
+    key.n = a.n;
+    key.p = a.p;
+    key.lda = a.lda;
+    key.ldb = a.ldb;
+    key.ldc = a.ldc;
+    key.alpha = canon(a.alpha, a.p);
+    key.beta = canon(a.beta, a.p);
+    key.dtype = a.dtype;
+    key.table = res.table;
+    key.levels = res.levels;
+    key.fuse = (a.flags & WS_FLAG_NOFUSE) ? 0 : 1;
+    return WS_OK;
+}
+
+static void fill_stats(const Plan &plan, const ws_args &a, ws_stats &s) {
+    s.workspace_bytes = (uint64_t)plan.ws_elems * 8u;
+    s.add_launches = (uint64_t)plan.add_ops;
+    s.gemm_launches = (uint64_t)plan.gemm_ops;
+    s.element_additions = (uint64_t)plan.element_additions;
+    s.base_flops = (uint64_t)plan.base_flops;
+    s.rows = (uint64_t)plan.rows;
+    s.levels = (uint64_t)plan.key.levels;
+    s.schedule = plan.key.table;
+    s.base = a.base;
+}
+
+// Launch every operation of a plan on `stream`.
+int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, bool trace) {
+    DevBufs bufs{{a.A, a.B, a.C, ws}};
+    std::vector<hipEvent_t> ev;
+    if (trace) {
+        ev.resize(plan.ops.size() + 1);
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess)
+                return fail(WS_EHIP, "hipEventCreate failed");
+        (void)hipEventRecord(ev[0], stream);
+    }
+    for (size_t i = 0; i < plan.ops.size(); ++i) {
+        const OpDesc &op = plan.ops[i];
+        hipError_t err;
+        if (op.kind == WS_OP_ADD)
+            err = launch_add(op, bufs, a.dtype, a.p, stream);
+        else if (a.base == WS_BASE_I8_LIMBS)
+            err = launch_gemm_limbs(op, bufs, a.dtype, a.p, stream);
+        else
+            err = launch_gemm(op, bufs, a.dtype, a.p, stream);
+        if (err != hipSuccess)
+            return fail(WS_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(err));
+        if (trace)
+            (void)hipEventRecord(ev[i + 1], stream);
+    }
+    if (trace) {
+        if (hipEventSynchronize(ev.back()) != hipSuccess)
+            return fail(WS_EHIP, "hipEventSynchronize failed");
+        for (size_t i = 0; i < plan.ops.size(); ++i) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            const OpDesc &op = plan.ops[i];
+            if (op.kind == WS_OP_ADD) {
+                g_trace.add_launches += 1;
+                g_trace.add_ms += ms;
+                g_trace.add_bytes += 8.0 * (double)(op.nin + op.nout) * (double)op.out[0].rows *
+                                     (double)op.out[0].cols;
+            } else {
+                g_trace.gemm_launches += 1;
+                g_trace.gemm_ms += ms;
+                g_trace.gemm_flops += 2.0 * (double)op.a.rows * (double)op.a.cols * (double)op.b.cols;
+            }
+        }
+        for (auto &e : ev)
+            (void)hipEventDestroy(e);
+    }
+    return WS_OK;
+}
+
+int execute(const ws_args &a, const PlanKey &key) {
+    std::shared_ptr<Plan> plan;
+    try {
+        plan = get_plan(key);
+    } catch (const std::exception &e) {
+        return fail(WS_EINVAL, std::string("planner: ") + e.what());
+    }
+    hipStream_t stream = a.stream ? static_cast<hipStream_t>(a.stream) : g_stream;
+    const size_t ws_bytes = (size_t)plan->ws_elems * 8u;
+    void *ws = nullptr;
+    bool owned = false;
+    if (ws_bytes) {
+        if (a.workspace) {
+            if (a.workspace_bytes < ws_bytes)
+                return fail(WS_ENOMEM, "attached workspace smaller than the schedule needs");
+            ws = a.workspace;
+        } else {
+            std::lock_guard<std::mutex> lock(g_mu);
+            if (g_ws && g_ws_bytes >= ws_bytes)
+                ws = g_ws;
+        }
+        if (!ws) {
+            if (hipMallocAsync(&ws, ws_bytes, stream) != hipSuccess)
+                return fail(WS_ENOMEM, "workspace allocation failed");
+            owned = true;
+        }
+    }
+    if (a.flags & WS_FLAG_CHECK) {
+        const int rc = check_ranges(a, stream);
+        if (rc != WS_OK) {
+            if (owned)
+                (void)hipFreeAsync(ws, stream);
+            return rc;
+        }
+    }
+    const int rc = run_plan(*plan, a, ws, stream, (a.flags & WS_FLAG_TRACE) != 0);
+    if (owned)
+        (void)hipFreeAsync(ws, stream);
+    fill_stats(*plan, a, g_stats);
+    g_stats.internal_alloc_bytes = owned ? ws_bytes : 0;
+    if (g_stats.workspace_bytes > g_stats.peak_temp_bytes)
+        g_stats.peak_temp_bytes = g_stats.workspace_bytes;
+    return rc;
+}
+
+// WS_FLAG_CHECK: every entry of A, B (and C when beta != 0) in [0, p).
+int check_ranges(const ws_args &a, hipStream_t stream) {
+    static std::mutex mu;
+    static int *flag_dev[64] = {nullptr};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(WS_EHIP, "hipGetDevice failed");
+    int *flag;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (!flag_dev[dev] && hipMalloc(&flag_dev[dev], sizeof(int)) != hipSuccess)
+            return fail(WS_EHIP, "hipMalloc of the check flag failed");
+        flag = flag_dev[dev];
+    }
+    if (hipMemsetAsync(flag, 0, sizeof(int), stream) != hipSuccess)
+        return fail(WS_EHIP, "hipMemsetAsync failed");
+    hipError_t e = launch_range_check(a.A, a.m, a.k, a.lda, a.dtype, a.p, flag, stream);
+    if (e == hipSuccess)
+        e = launch_range_check(a.B, a.k, a.n, a.ldb, a.dtype, a.p, flag, stream);
+    if (e == hipSuccess && canon(a.beta, a.p) != 0)
+        e = launch_range_check(a.C, a.m, a.n, a.ldc, a.dtype, a.p, flag, stream);
+    int host = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&host, flag, sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(stream);
+    if (e != hipSuccess)
+        return fail(WS_EHIP, std::string("range check failed: ") + hipGetErrorString(e));
+    if (host)
+        return fail(WS_ERANGE, "an entry of A, B or C is not a residue in [0, p)");
+    return WS_OK;
+}
+
+}  // namespace wsmul
+
+extern "C" {
+
+int wsmul_mod_p_ex(const ws_args *args) {
+    ws_args a;
+    PlanKey key;
+    Resolved res;
+    int rc = prepare(args, a, key, res);
+    if (rc != WS_OK)
+        return rc;
+    if (a.m == 0 || a.n == 0) {
+        g_stats.workspace_bytes = 0;
+        return WS_OK;
+    }
+    return execute(a, key);
+}
+
+static int simple_call(int dtype, int64_t m, int64_t k, int64_t n, int64_t p, void *A, void *B,
+                       void *C, int64_t alpha, int64_t beta, int schedule, int levels) {
+    ws_args a;
+    std::memset(&a, 0, sizeof(a));
+    a.m = m;
+    a.k = k;
+    a.n = n;
+    a.p = p;
+    a.A = A;
+    a.B = B;
+    a.C = C;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.dtype = dtype;
+    a.schedule = schedule;
+    a.levels = levels;
+    a.base = WS_BASE_F64_MFMA;
+    return wsmul_mod_p_ex(&a);
+}
+
+int wsmul_mod_p(int64_t m, int64_t k, int64_t n, int64_t p, void *A, void *B, void *C,
+                int64_t alpha, int64_t beta, int schedule, int levels) {
+    return simple_call(WS_F64, m, k, n, p, A, B, C, alpha, beta, schedule, levels);
+}
+
+int wsmul_mod_p_i64(int64_t m, int64_t k, int64_t n, int64_t p, void *A, void *B, void *C,
+                    int64_t alpha, int64_t beta, int schedule, int levels) {
+    return simple_call(WS_I64, m, k, n, p, A, B, C, alpha, beta, schedule, levels);
+}
+
+size_t wsmul_workspace_bytes(int64_t m, int64_t k, int64_t n, int dtype, int schedule, int levels,
+                             int beta_nonzero) {
+    if (m < 0 || k < 0 || n < 0 || (dtype != WS_F64 && dtype != WS_I64)) {
+        set_error("bad dimensions or dtype");
+        return 0;
+    }
+    Resolved r = resolve_schedule(schedule, m, k, n, beta_nonzero != 0, levels);
+    if (r.status != WS_OK) {
+        set_error(r.error);
+        return 0;
+    }
+    if (m == 0 || n == 0)
+        return 0;
+    try {
+        return (size_t)workspace_elems(r.table, m, k, n, r.levels) * 8u;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return 0;
+    }
+}
+
+int wsmul_plan_info(const ws_args *args, ws_stats *stats) {
+    ws_args a;
+    PlanKey key;
+    Resolved res;
+    if (!stats)
+        return fail(WS_EINVAL, "null stats");
+    ws_args probe = args ? *args : ws_args{};
+    // Pointers are not dereferenced: stand-ins keep the null checks quiet.
+    static char dummy[16];
+    if (!probe.A) probe.A = dummy;
+    if (!probe.B) probe.B = dummy;
+    if (!probe.C) probe.C = dummy;
+    int rc = prepare(&probe, a, key, res);
+    if (rc != WS_OK)
+        return rc;
+    std::memset(stats, 0, sizeof(*stats));
+    if (a.m == 0 || a.n == 0)
+        return WS_OK;
+    try {
+        auto plan = get_plan(key);
+        fill_stats(*plan, a, *stats);
+    } catch (const std::exception &e) {
+        return fail(WS_EINVAL, std::string("planner: ") + e.what());
+    }
+    return WS_OK;
+}
+
+int wsmul_plan_export(const ws_args *args, ws_op_desc *ops, int64_t cap, int64_t *count) {
+    ws_args a;
+    PlanKey key;
+    Resolved res;
+    if (!count || (cap > 0 && !ops))
+        return fail(WS_EINVAL, "null output");
+    ws_args probe = args ? *args : ws_args{};
+    static char dummy[16];
+    if (!probe.A) probe.A = dummy;
+    if (!probe.B) probe.B = dummy;
+    if (!probe.C) probe.C = dummy;
+    int rc = prepare(&probe, a, key, res);
+    if (rc != WS_OK)
+        return rc;
+    *count = 0;
+    if (a.m == 0 || a.n == 0)
+        return WS_OK;
+    try {
+        auto plan = get_plan(key);
+        *count = (int64_t)plan->ops.size();
+        for (int64_t i = 0; i < cap && i < *count; ++i)
+            ops[i] = plan->ops[i];
+    } catch (const std::exception &e) {
+        return fail(WS_EINVAL, std::string("planner: ") + e.what());
+    }
+    return WS_OK;
+}
+
+int wsmul_set_workspace(void *ptr, size_t bytes) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_ws = bytes ? ptr : nullptr;
+    g_ws_bytes = ptr ? bytes : 0;
+    return WS_OK;
+}
+
+int wsmul_set_stream(void *stream) {
+    g_stream = static_cast<hipStream_t>(stream);
+    return WS_OK;
+}
+
+int wsmul_get_stats(ws_stats *out) {
+    if (!out)
+        return fail(WS_EINVAL, "null stats");
+    *out = g_stats;
+    return WS_OK;
+}
+
+int wsmul_reset_stats(void) {
+    std::memset(&g_stats, 0, sizeof(g_stats));
+    std::memset(&g_trace, 0, sizeof(g_trace));
+    return WS_OK;
+}
+
+int wsmul_get_trace(ws_trace *out) {
+    if (!out)
+        return fail(WS_EINVAL, "null trace");
+    *out = g_trace;
+    return WS_OK;
+}
+
+const char *wsmul_last_error(void) { return g_err.c_str(); }
+
+const char *wsmul_schedule_name(int table) {
+    switch (table) {
+    case TAB_CLASSICAL: return "classical";
+    case TAB_T1: return "table1-two-temporaries";
+    case TAB_HL: return "table2-three-temporaries";
+    case TAB_IP: return "table3-in-place-overwrite";
+    case TAB_OVR: return "table5-overwrite-B";
+    case TAB_ACLR: return "table6-accumulate-overwrite";
+    case TAB_ACCR: return "table7-accumulate-overwrite-B";
+    case TAB_ACC: return "table9-accumulate-two-temporaries";
+    case TAB_IPMM: return "algorithm2-read-only-in-place";
+    default: return "unknown";
+    }
+}
+
+const char *wsmul_version(void) { return "wsmul 0.1 (gfx950)"; }
+
+}  // extern "C"

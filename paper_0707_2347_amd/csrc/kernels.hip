@@ -1,0 +1,606 @@
+// HIP kernels for gfx950: fused addition rows and the binary64 matrix-core
+// base product with its fused epilogue.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace wsmul {
+
+// ===================================================================== adds
+// One launch executes a group of consecutive addition rows of a schedule:
+// for every element position, out[o] <- sum_i coef[o][i] * in[i] (mod p).
+// Inputs are all loaded before any output is stored, which is what makes the
+// group equal to running its rows one after the other (the planner only
+// groups views that are identical or disjoint).  HBM-bound: each thread moves
+// VEC consecutive elements per input and output with 16-byte accesses.
+struct LinParams {
+    const void *in[WS_MAX_IN];
+    int64_t ldi[WS_MAX_IN];
+    void *out[WS_MAX_OUT];
+    int64_t ldo[WS_MAX_OUT];
+    double coef[WS_MAX_OUT][WS_MAX_IN];
+    int32_t nout;
+    uint32_t items;  // rows * cols / VEC
+    FastDiv per_row; // cols / VEC
+    double p, pinv;
+};
+
+template <typename T, int VEC, int NI>
+__global__ __launch_bounds__(256) void lincomb_kernel(LinParams P) {
+    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
+    if (idx >= P.items)
+        return;
+    const uint32_t r = P.per_row.div(idx);
+    const int64_t c = (int64_t)(idx - r * P.per_row.d) * VEC;
+    double x[NI][VEC];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const T *src = static_cast<const T *>(P.in[i]) + (int64_t)r * P.ldi[i] + c;
+        if constexpr (VEC == 2)
+            load2(src, x[i][0], x[i][1]);
+        else
+            x[i][0] = to_f64(src[0]);
+    }
+#pragma unroll
+    for (int o = 0; o < WS_MAX_OUT; ++o) {
+        if (o >= P.nout)
+            break;
+        T *dst = static_cast<T *>(P.out[o]) + (int64_t)r * P.ldo[o] + c;
+        double y[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+                acc = fma(P.coef[o][i], x[i][v], acc);
+            y[v] = mod_reduce(acc, P.p, P.pinv);
+        }
+        if constexpr (VEC == 2)
+            store2(dst, y[0], y[1]);
+        else
+            dst[0] = from_f64<T>(y[0]);
+    }
+}
+
+template <typename T, int VEC>
+static hipError_t launch_lin_t(const LinParams &P, int nin, hipStream_t s) {
+    const dim3 grid((P.items + 255) / 256), block(256);
+    switch (nin) {
+#define WS_LIN_CASE(N) \
+    case N: hipLaunchKernelGGL((lincomb_kernel<T, VEC, N>), grid, block, 0, s, P); break;
+        WS_LIN_CASE(1) WS_LIN_CASE(2) WS_LIN_CASE(3) WS_LIN_CASE(4)
+        WS_LIN_CASE(5) WS_LIN_CASE(6) WS_LIN_CASE(7) WS_LIN_CASE(8)
+#undef WS_LIN_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+hipError_t launch_add(const ws_op_desc &op, const DevBufs &bufs, int dtype, int64_t p,
+                      hipStream_t stream) {
+    const int64_t rows = op.out[0].rows, cols = op.out[0].cols;
+    if (rows == 0 || cols == 0)
+        return hipSuccess;
+    const size_t esz = 8;
+    LinParams P{};
+    bool vec2 = (cols % 2) == 0;
+    for (int i = 0; i < op.nin; ++i) {
+        const ws_view &v = op.in[i];
+        P.in[i] = static_cast<const char *>(bufs.ptr[v.buf]) + v.off * esz;
+        P.ldi[i] = v.ld;
+        vec2 = vec2 && (v.ld % 2 == 0) && aligned16(P.in[i]);
+    }
+    for (int o = 0; o < op.nout; ++o) {
+        const ws_view &v = op.out[o];
+        P.out[o] = static_cast<char *>(bufs.ptr[v.buf]) + v.off * esz;
+        P.ldo[o] = v.ld;
+        vec2 = vec2 && (v.ld % 2 == 0) && aligned16(P.out[o]);
+        for (int i = 0; i < op.nin; ++i)
+            P.coef[o][i] = (double)op.coef[o][i];
+    }
+    P.nout = op.nout;
+    P.p = (double)p;
+    P.pinv = 1.0 / (double)p;
+    const int vec = vec2 ? 2 : 1;
+    const uint64_t items = (uint64_t)rows * (uint64_t)(cols / vec);
+    if (items >= (uint64_t(1) << 32))
+        return hipErrorInvalidValue;
+    P.items = (uint32_t)items;
+    P.per_row.init((uint32_t)(cols / vec));
+    if (dtype == WS_I64)
+        return vec2 ? launch_lin_t<int64_t, 2>(P, op.nin, stream)
+                    : launch_lin_t<int64_t, 1>(P, op.nin, stream);
+    return vec2 ? launch_lin_t<double, 2>(P, op.nin, stream)
+                : launch_lin_t<double, 1>(P, op.nin, stream);
+}
+
+// ==================================================================== gemm
+// Base product D-group <- alpha*A*B (mod p) on the binary64 matrix cores
+// (v_mfma_f64_16x16x4_f64), then the epilogue group of addition rows fused
+// behind it.  Entries are integers, so every partial sum is exact while it
+// stays below 2^53; the accumulators are folded back to residues every
+// `kc_tiles` K-tiles, and operands are centred into (-p/2, p/2] when p is
+// large enough for that to lengthen the fold period.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct GemmParams {
+    const void *A;
+    const void *B;
+    int64_t lda, ldb;
+    int64_t M, N, K;
+    double p, pinv, half, alpha;
+    int32_t kc_tiles;   // fold period in K-tiles of the kernel (0 = only at the end)
+    int32_t tiles_m, tiles_n;
+    int32_t nin, nout;
+    const void *ein[WS_MAX_IN];
+    int64_t eldi[WS_MAX_IN];
+    void *eout[WS_MAX_OUT];
+    int64_t eldo[WS_MAX_OUT];
+    double coef[WS_MAX_OUT][WS_MAX_IN];
+};
+
+// Workgroup ids are dealt round-robin to the 8 XCDs; renumber them so that
+// consecutive tile numbers run on one XCD (sharing its L2), then walk tiles
+// in bands of 8 tile-rows so neighbouring workgroups share A and B panels.
+__device__ __forceinline__ void tile_of(int32_t tiles_m, int32_t tiles_n, int32_t &tm,
+                                        int32_t &tn) {
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    const uint32_t q = G / 8, r = G % 8, x = b % 8;
+    const uint32_t pid = x * q + min(x, r) + b / 8;
+    const int32_t band = 8;
+    const int32_t per_band = band * tiles_n;
+    const int32_t g = pid / per_band;
+    const int32_t first = g * band;
+    const int32_t rows_here = min(band, tiles_m - first);
+    const int32_t in_band = pid % per_band;
+    tm = first + in_band % rows_here;
+    tn = in_band / rows_here;
+}
+
+template <typename T>
+__device__ __forceinline__ double centred(T raw, double p, double half, bool centre) {
+    double x = to_f64(raw);
+    return (centre && x > half) ? x - p : x;
+}
+
+// Product of one element, reduced: alpha * (acc mod p) mod p, where acc is
+// the exact dot product (|acc| < 2^53).
+__device__ __forceinline__ double product_residue(const GemmParams &P, double acc) {
+    return mod_reduce(P.alpha * mod_reduce(acc, P.p, P.pinv), P.p, P.pinv);
+}
+
+// Epilogue for one element: prod is the reduced product, input 0 of the
+// fused group; the other inputs are read at (row, col) and every output of
+// the group is stored there.
+template <typename T>
+__device__ __forceinline__ void epilogue_apply(const GemmParams &P, double prod, int64_t row,
+                                               int64_t col) {
+    double x[WS_MAX_IN];
+    x[0] = prod;
+#pragma unroll
+    for (int i = 1; i < WS_MAX_IN; ++i)
+        if (i < P.nin)
+            x[i] = to_f64(static_cast<const T *>(P.ein[i])[row * P.eldi[i] + col]);
+#pragma unroll
+    for (int o = 0; o < WS_MAX_OUT; ++o) {
+        if (o >= P.nout)
+            break;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < WS_MAX_IN; ++i)
+            if (i < P.nin)
+                s = fma(P.coef[o][i], x[i], s);
+        static_cast<T *>(P.eout[o])[row * P.eldo[o] + col] = from_f64<T>(mod_reduce(s, P.p, P.pinv));
+    }
+}
+
+// ---- LDS-tiled kernel: BM x BN tile per workgroup, four waves in a 2 x 2
+// grid, each wave (BM/2) x (BN/2) of 16 x 16 matrix-core tiles, K-tiles of 16
+// double-buffered through LDS.  In the matrix-core step s of a K-tile, lane l
+// supplies k = 4*(l/16) + s, so each lane's four A values are contiguous in
+// LDS; B uses the same k assignment.
+template <typename T, int BM, int BN, bool CENTRE, bool VEC2>
+__global__ __launch_bounds__(256) void gemm_lds_kernel(GemmParams P) {
+    constexpr int BK = 16, APAD = 2;
+    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+    constexpr int AST = BK + APAD;                       // A row stride in LDS
+    __shared__ double As[2][BM * AST];
+    __shared__ double Bs[2][BK * BN];
+
+    int32_t tm, tn;
+    tile_of(P.tiles_m, P.tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int li = lane & 15, kq = lane >> 4;
+
+    const T *A = static_cast<const T *>(P.A);
+    const T *B = static_cast<const T *>(P.B);
+
+    // Global -> register staging: A tile BM x 16, B tile 16 x BN, two
+    // elements per access.
+    constexpr int A_PAIRS = BM * BK / 2 / 256;   // per thread
+    constexpr int B_PAIRS = BK * BN / 2 / 256;
+    double ra[A_PAIRS][2], rb[B_PAIRS][2];
+
+    auto gload = [&](int64_t k0) {
+#pragma unroll
+        for (int j = 0; j < A_PAIRS; ++j) {
+            const int v = tid + 256 * j, row = v / (BK / 2), cp = v % (BK / 2);
+            const int64_t gr = m0 + row, gk = k0 + 2 * cp;
+            double x0 = 0.0, x1 = 0.0;
+            if (gr < P.M) {
+                const T *src = A + gr * P.lda + gk;
+                if (VEC2) {
+                    if (gk < P.K)
+                        load2(src, x0, x1);
+                } else {
+                    if (gk < P.K)
+                        x0 = to_f64(src[0]);
+                    if (gk + 1 < P.K)
+                        x1 = to_f64(src[1]);
+                }
+            }
+            ra[j][0] = (CENTRE && x0 > P.half) ? x0 - P.p : x0;
+            ra[j][1] = (CENTRE && x1 > P.half) ? x1 - P.p : x1;
+        }
+#pragma unroll
+        for (int j = 0; j < B_PAIRS; ++j) {
+            const int v = tid + 256 * j, kr = v / (BN / 2), np = v % (BN / 2);
+            const int64_t gk = k0 + kr, gn = n0 + 2 * np;
+            double x0 = 0.0, x1 = 0.0;
+            if (gk < P.K) {
+                const T *src = B + gk * P.ldb + gn;
+                if (VEC2) {
+                    if (gn < P.N)
+                        load2(src, x0, x1);
+                } else {
+                    if (gn < P.N)
+                        x0 = to_f64(src[0]);
+                    if (gn + 1 < P.N)
+                        x1 = to_f64(src[1]);
+                }
+            }
+            rb[j][0] = (CENTRE && x0 > P.half) ? x0 - P.p : x0;
+            rb[j][1] = (CENTRE && x1 > P.half) ? x1 - P.p : x1;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < A_PAIRS; ++j) {
+            const int v = tid + 256 * j, row = v / (BK / 2), cp = v % (BK / 2);
+            *reinterpret_cast<double2 *>(&As[buf][row * AST + 2 * cp]) = make_double2(ra[j][0], ra[j][1]);
+        }
+#pragma unroll
+        for (int j = 0; j < B_PAIRS; ++j) {
+            const int v = tid + 256 * j, kr = v / (BN / 2), np = v % (BN / 2);
+            *reinterpret_cast<double2 *>(&Bs[buf][kr * BN + 2 * np]) = make_double2(rb[j][0], rb[j][1]);
+        }
+    };
+
+    f64x4 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    auto fold = [&]() {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[i][j][v] = mod_reduce(acc[i][j][v], P.p, P.pinv);
+    };
+
+    const int64_t ktiles = (P.K + BK - 1) / BK;
+    if (ktiles > 0) {
+        gload(0);
+        sstore(0);
+    }
+    __syncthreads();
+    int since_fold = 0;
+    for (int64_t t = 0; t < ktiles; ++t) {
+        const int cur = (int)(t & 1);
+        if (t + 1 < ktiles)
+            gload((t + 1) * BK);
+        double af[FM][4];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            const double *src = &As[cur][(wm * WM + i * 16 + li) * AST + 4 * kq];
+            const double2 lo = *reinterpret_cast<const double2 *>(src);
+            const double2 hi = *reinterpret_cast<const double2 *>(src + 2);
+            af[i][0] = lo.x;
+            af[i][1] = lo.y;
+            af[i][2] = hi.x;
+            af[i][3] = hi.y;
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            double bf[FN];
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                bf[j] = Bs[cur][(4 * kq + s) * BN + wn * WN + j * 16 + li];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j], acc[i][j], 0, 0, 0);
+        }
+        if (t + 1 < ktiles)
+            sstore(cur ^ 1);
+        __syncthreads();
+        if (P.kc_tiles > 0 && ++since_fold == P.kc_tiles) {
+            fold();
+            since_fold = 0;
+        }
+    }
+
+    // Output layout of the 16 x 16 x 4 binary64 matrix-core op (measured on
+    // gfx950): lane l, accumulator element v holds row l/16 + 4*v of column
+    // l % 16.  The reduced products go
+    // through LDS (reusing the operand buffers) so that the fused epilogue
+    // reads and writes whole rows; a 128 x 128 tile takes two rounds, one per
+    // half of the wave grid.
+    constexpr int LDS_DOUBLES = 2 * BM * AST + 2 * BK * BN;
+    constexpr int ROUNDS = (BM * BN <= LDS_DOUBLES) ? 1 : 2;
+    static_assert(BM * BN / ROUNDS <= LDS_DOUBLES, "epilogue staging does not fit");
+    double *stage = &As[0][0];
+    static_assert(sizeof(As) + sizeof(Bs) == LDS_DOUBLES * sizeof(double), "layout");
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc[i][j][v] = product_residue(P, acc[i][j][v]);
+    constexpr int RROWS = BM / ROUNDS;
+#pragma unroll
+    for (int h = 0; h < ROUNDS; ++h) {
+        if (ROUNDS == 1 || wm == h) {
+            const int rbase = (ROUNDS == 1 ? wm * WM : 0);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        stage[(rbase + i * 16 + kq + 4 * v) * BN + wn * WN + j * 16 + li] = acc[i][j][v];
+        }
+        __syncthreads();
+        for (int e = tid; e < RROWS * BN; e += 256) {
+            const int r = e / BN, c = e % BN;
+            const int64_t row = m0 + h * RROWS + r, col = n0 + c;
+            if (row < P.M && col < P.N)
+                epilogue_apply<T>(P, stage[e], row, col);
+        }
+        __syncthreads();
+    }
+}
+
+// ---- Small products: a 32 x 32 output tile per workgroup, its four waves
+// splitting the K-tiles round-robin, operands read straight from global
+// memory, partial tiles summed through LDS.  This keeps all SIMDs busy when
+// the product has too few output tiles to fill the chip (deep recursion
+// levels).
+template <typename T, bool CENTRE>
+__global__ __launch_bounds__(256) void gemm_sk_kernel(GemmParams P) {
+    constexpr int BM = 32, BN = 32, BK = 16;
+    __shared__ double part[4][BM * BN];
+    int32_t tm, tn;
+    tile_of(P.tiles_m, P.tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, kq = lane >> 4;
+    const T *A = static_cast<const T *>(P.A);
+    const T *B = static_cast<const T *>(P.B);
+
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    const int64_t ktiles = (P.K + BK - 1) / BK;
+    int since_fold = 0;
+    for (int64_t t = wave; t < ktiles; t += 4) {
+        const int64_t k0 = t * BK + 4 * kq;
+        double af[2][4], bf[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int64_t gr = m0 + i * 16 + li;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int64_t gk = k0 + s;
+                af[i][s] = (gr < P.M && gk < P.K)
+                               ? centred(A[gr * P.lda + gk], P.p, P.half, CENTRE) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t gn = n0 + j * 16 + li;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int64_t gk = k0 + s;
+                bf[j][s] = (gn < P.N && gk < P.K)
+                               ? centred(B[gk * P.ldb + gn], P.p, P.half, CENTRE) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+        if (P.kc_tiles > 0 && ++since_fold == P.kc_tiles) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[i][j][v] = mod_reduce(acc[i][j][v], P.p, P.pinv);
+            since_fold = 0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                part[wave][(i * 16 + kq + 4 * v) * BN + j * 16 + li] =
+                    mod_reduce(acc[i][j][v], P.p, P.pinv);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int idx = tid + 256 * e;
+        const int r = idx / BN, c = idx % BN;
+        const double s = part[0][idx] + part[1][idx] + part[2][idx] + part[3][idx];
+        const int64_t row = m0 + r, col = n0 + c;
+        if (row < P.M && col < P.N)
+            epilogue_apply<T>(P, product_residue(P, s), row, col);
+    }
+}
+
+// Fold period: the largest number of K-tiles t with
+// t*16*m^2 + 2p < 2^53 where m bounds |operand| (p-1, or (p-1)/2 centred).
+static int32_t fold_tiles(int64_t p, bool centre, int64_t K) {
+    const double mx = centre ? (double)((p - 1) / 2 + 1) : (double)(p - 1);
+    const double lim = 9007199254740992.0 - 4.0 * (double)p;
+    const double per_tile = 16.0 * mx * mx;
+    const double t = std::floor(lim / std::max(per_tile, 1.0));
+    if (t * 16.0 >= (double)K + 16.0)
+        return 0;  // the whole inner dimension fits: fold only at the end
+    return (int32_t)std::max(1.0, std::min(t, 1.0e9));
+}
+
+template <typename T>
+static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
+    const int64_t big = ((P.M + 127) / 128) * ((P.N + 127) / 128);
+    const int64_t mid = ((P.M + 63) / 64) * ((P.N + 63) / 64);
+    const bool centre = fold_tiles((int64_t)P.p, false, P.K) != 0;
+    P.kc_tiles = fold_tiles((int64_t)P.p, centre, P.K);
+    P.half = std::floor(P.p / 2.0);
+    if (big >= 512) {
+        P.tiles_m = (int32_t)((P.M + 127) / 128);
+        P.tiles_n = (int32_t)((P.N + 127) / 128);
+        const dim3 grid((uint32_t)big), block(256);
+        if (centre) {
+            if (vec2) hipLaunchKernelGGL((gemm_lds_kernel<T, 128, 128, true, true>), grid, block, 0, s, P);
+            else hipLaunchKernelGGL((gemm_lds_kernel<T, 128, 128, true, false>), grid, block, 0, s, P);
+        } else {
+            if (vec2) hipLaunchKernelGGL((gemm_lds_kernel<T, 128, 128, false, true>), grid, block, 0, s, P);
+            else hipLaunchKernelGGL((gemm_lds_kernel<T, 128, 128, false, false>), grid, block, 0, s, P);
+        }
+    } else if (mid >= 256) {
+        P.tiles_m = (int32_t)((P.M + 63) / 64);
+        P.tiles_n = (int32_t)((P.N + 63) / 64);
+        const dim3 grid((uint32_t)mid), block(256);
+        if (centre) {
+            if (vec2) hipLaunchKernelGGL((gemm_lds_kernel<T, 64, 64, true, true>), grid, block, 0, s, P);
+            else hipLaunchKernelGGL((gemm_lds_kernel<T, 64, 64, true, false>), grid, block, 0, s, P);
+        } else {
+            if (vec2) hipLaunchKernelGGL((gemm_lds_kernel<T, 64, 64, false, true>), grid, block, 0, s, P);
+            else hipLaunchKernelGGL((gemm_lds_kernel<T, 64, 64, false, false>), grid, block, 0, s, P);
+        }
+    } else {
+        P.tiles_m = (int32_t)((P.M + 31) / 32);
+        P.tiles_n = (int32_t)((P.N + 31) / 32);
+        const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(256);
+        if (centre) hipLaunchKernelGGL((gemm_sk_kernel<T, true>), grid, block, 0, s, P);
+        else hipLaunchKernelGGL((gemm_sk_kernel<T, false>), grid, block, 0, s, P);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(const ws_op_desc &op, const DevBufs &bufs, int dtype, int64_t p,
+                       hipStream_t stream) {
+    const int64_t M = op.a.rows, K = op.a.cols, N = op.b.cols;
+    if (M == 0 || N == 0)
+        return hipSuccess;
+    const size_t esz = 8;
+    GemmParams P{};
+    P.A = static_cast<const char *>(bufs.ptr[op.a.buf]) + op.a.off * esz;
+    P.B = static_cast<const char *>(bufs.ptr[op.b.buf]) + op.b.off * esz;
+    P.lda = op.a.ld;
+    P.ldb = op.b.ld;
+    P.M = M;
+    P.N = N;
+    P.K = K;
+    P.p = (double)p;
+    P.pinv = 1.0 / (double)p;
+    P.alpha = (double)op.alpha;
+    P.nin = op.nin;
+    P.nout = op.nout;
+    for (int i = 1; i < op.nin; ++i) {
+        P.ein[i] = static_cast<const char *>(bufs.ptr[op.in[i].buf]) + op.in[i].off * esz;
+        P.eldi[i] = op.in[i].ld;
+    }
+    for (int o = 0; o < op.nout; ++o) {
+        P.eout[o] = static_cast<char *>(bufs.ptr[op.out[o].buf]) + op.out[o].off * esz;
+        P.eldo[o] = op.out[o].ld;
+        for (int i = 0; i < op.nin; ++i)
+            P.coef[o][i] = (double)op.coef[o][i];
+    }
+    const bool vec2 = (K % 2 == 0) && (N % 2 == 0) && (P.lda % 2 == 0) && (P.ldb % 2 == 0) &&
+                      aligned16(P.A) && aligned16(P.B);
+    if ((M + 31) / 32 * ((N + 31) / 32) >= (int64_t(1) << 31))
+        return hipErrorInvalidValue;
+    return dtype == WS_I64 ? launch_gemm_t<int64_t>(P, vec2, stream)
+                           : launch_gemm_t<double>(P, vec2, stream);
+}
+
+}  // namespace wsmul
+
+namespace wsmul {
+
+// ============================================================ range check
+template <typename T>
+__global__ __launch_bounds__(256) void range_check_kernel(const T *ptr, int64_t rows,
+                                                          int64_t cols, int64_t ld, double p,
+                                                          int *flag) {
+    const int64_t total = rows * cols;
+    for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * 256) {
+        const int64_t r = idx / cols, c = idx % cols;
+        const T raw = ptr[r * ld + c];
+        bool bad;
+        if constexpr (sizeof(T) == 8 && T(0.5) != T(0)) {
+            const double x = (double)raw;
+            bad = !(x >= 0.0 && x < p && x == floor(x));
+        } else {
+            bad = raw < 0 || (double)raw >= p;
+        }
+        if (bad)
+            *flag = 1;
+    }
+}
+
+hipError_t launch_range_check(const void *ptr, int64_t rows, int64_t cols, int64_t ld,
+                              int dtype, int64_t p, int *flag, hipStream_t stream) {
+    if (rows == 0 || cols == 0)
+        return hipSuccess;
+    const int64_t total = rows * cols;
+    const uint32_t blocks = (uint32_t)std::min<int64_t>((total + 255) / 256, 4096);
+    if (dtype == WS_I64)
+        hipLaunchKernelGGL(range_check_kernel<int64_t>, dim3(blocks), dim3(256), 0, stream,
+                           static_cast<const int64_t *>(ptr), rows, cols, ld, (double)p, flag);
+    else
+        hipLaunchKernelGGL(range_check_kernel<double>, dim3(blocks), dim3(256), 0, stream,
+                           static_cast<const double *>(ptr), rows, cols, ld, (double)p, flag);
+    return hipGetLastError();
+}
+
+}  // namespace wsmul

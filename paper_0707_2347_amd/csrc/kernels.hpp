@@ -1,0 +1,28 @@
+// Host-side launchers of the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "wsmul.h"
+
+namespace wsmul {
+
+// Base pointers of the four buffers a plan refers to (WS_BUF_A .. WS_BUF_W).
+struct DevBufs {
+    void *ptr[4];
+};
+
+// One fused group of addition rows (elementwise, HBM-bound).
+hipError_t launch_add(const ws_op_desc &op, const DevBufs &bufs, int dtype, int64_t p,
+                      hipStream_t stream);
+
+// One base product with its epilogue group (binary64 matrix cores).
+hipError_t launch_gemm(const ws_op_desc &op, const DevBufs &bufs, int dtype, int64_t p,
+                       hipStream_t stream);
+
+// Sets *flag to 1 if some entry of the rows x cols view is not an integer in
+// [0, p).  The flag must be cleared by the caller beforehand.
+hipError_t launch_range_check(const void *ptr, int64_t rows, int64_t cols, int64_t ld,
+                              int dtype, int64_t p, int *flag, hipStream_t stream);
+
+}  // namespace wsmul
