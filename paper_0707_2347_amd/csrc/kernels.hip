@@ -29,49 +29,66 @@ struct LinParams {
     double p, pinv;
 };
 
-template <typename T, int VEC, int NI>
+template <typename T, int VEC, int NI, int ITEMS>
 __global__ __launch_bounds__(256) void lincomb_kernel(LinParams P) {
-    const uint32_t idx = blockIdx.x * 256u + threadIdx.x;
-    if (idx >= P.items)
-        return;
-    const uint32_t r = P.per_row.div(idx);
-    const int64_t c = (int64_t)(idx - r * P.per_row.d) * VEC;
-    double x[NI][VEC];
+    // ITEMS vector items per thread, a grid-size apart (every load instruction
+    // of a wave stays contiguous); all loads are issued before any store.
+    const uint32_t stride = gridDim.x * 256u;
+    const uint32_t first = blockIdx.x * 256u + threadIdx.x;
+    double x[ITEMS][NI][VEC];
+    int64_t rr[ITEMS], cc[ITEMS];
+    bool ok[ITEMS];
 #pragma unroll
-    for (int i = 0; i < NI; ++i) {
-        const T *src = static_cast<const T *>(P.in[i]) + (int64_t)r * P.ldi[i] + c;
-        if constexpr (VEC == 2)
-            load2(src, x[i][0], x[i][1]);
-        else
-            x[i][0] = to_f64(src[0]);
+    for (int it = 0; it < ITEMS; ++it) {
+        const uint32_t idx = first + it * stride;
+        ok[it] = idx < P.items;
+        const uint32_t r = P.per_row.div(ok[it] ? idx : 0u);
+        rr[it] = r;
+        cc[it] = (int64_t)((ok[it] ? idx : 0u) - r * P.per_row.d) * VEC;
+        if (!ok[it])
+            continue;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const T *src = static_cast<const T *>(P.in[i]) + rr[it] * P.ldi[i] + cc[it];
+            if constexpr (VEC == 2)
+                load2(src, x[it][i][0], x[it][i][1]);
+            else
+                x[it][i][0] = to_f64(src[0]);
+        }
     }
 #pragma unroll
-    for (int o = 0; o < WS_MAX_OUT; ++o) {
-        if (o >= P.nout)
-            break;
-        T *dst = static_cast<T *>(P.out[o]) + (int64_t)r * P.ldo[o] + c;
-        double y[VEC];
+    for (int it = 0; it < ITEMS; ++it) {
+        if (!ok[it])
+            continue;
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-            double acc = 0.0;
+        for (int o = 0; o < WS_MAX_OUT; ++o) {
+            if (o >= P.nout)
+                break;
+            T *dst = static_cast<T *>(P.out[o]) + rr[it] * P.ldo[o] + cc[it];
+            double y[VEC];
 #pragma unroll
-            for (int i = 0; i < NI; ++i)
-                acc = fma(P.coef[o][i], x[i][v], acc);
-            y[v] = mod_reduce(acc, P.p, P.pinv);
+            for (int v = 0; v < VEC; ++v) {
+                double acc = 0.0;
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+                    acc = fma(P.coef[o][i], x[it][i][v], acc);
+                y[v] = mod_reduce(acc, P.p, P.pinv);
+            }
+            if constexpr (VEC == 2)
+                store2(dst, y[0], y[1]);
+            else
+                dst[0] = from_f64<T>(y[0]);
         }
-        if constexpr (VEC == 2)
-            store2(dst, y[0], y[1]);
-        else
-            dst[0] = from_f64<T>(y[0]);
     }
 }
 
-template <typename T, int VEC>
-static hipError_t launch_lin_t(const LinParams &P, int nin, hipStream_t s) {
-    const dim3 grid((P.items + 255) / 256), block(256);
+template <typename T, int VEC, int ITEMS>
+static hipError_t launch_lin_items(const LinParams &P, int nin, hipStream_t s) {
+    const uint32_t threads = (P.items + ITEMS - 1) / ITEMS;
+    const dim3 grid((threads + 255) / 256), block(256);
     switch (nin) {
 #define WS_LIN_CASE(N) \
-    case N: hipLaunchKernelGGL((lincomb_kernel<T, VEC, N>), grid, block, 0, s, P); break;
+    case N: hipLaunchKernelGGL((lincomb_kernel<T, VEC, N, ITEMS>), grid, block, 0, s, P); break;
         WS_LIN_CASE(1) WS_LIN_CASE(2) WS_LIN_CASE(3) WS_LIN_CASE(4)
         WS_LIN_CASE(5) WS_LIN_CASE(6) WS_LIN_CASE(7) WS_LIN_CASE(8)
 #undef WS_LIN_CASE
@@ -79,6 +96,15 @@ static hipError_t launch_lin_t(const LinParams &P, int nin, hipStream_t s) {
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Large blocks: several items per thread keep more bytes in flight per wave;
+// small blocks: one item per thread keeps every CU busy.
+template <typename T, int VEC>
+static hipError_t launch_lin_t(const LinParams &P, int nin, hipStream_t s) {
+    if (P.items >= (1u << 21))
+        return launch_lin_items<T, VEC, 4>(P, nin, s);
+    return launch_lin_items<T, VEC, 1>(P, nin, s);
 }
 
 static bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -110,7 +136,7 @@ hipError_t launch_add(const ws_op_desc &op, const DevBufs &bufs, int dtype, int6
     P.pinv = 1.0 / (double)p;
     const int vec = vec2 ? 2 : 1;
     const uint64_t items = (uint64_t)rows * (uint64_t)(cols / vec);
-    if (items >= (uint64_t(1) << 32))
+    if (items >= (uint64_t(1) << 31))
         return hipErrorInvalidValue;
     P.items = (uint32_t)items;
     P.per_row.init((uint32_t)(cols / vec));
@@ -176,18 +202,20 @@ __device__ __forceinline__ double product_residue(const GemmParams &P, double ac
     return mod_reduce(P.alpha * mod_reduce(acc, P.p, P.pinv), P.p, P.pinv);
 }
 
-// Epilogue for one element: prod is the reduced product, input 0 of the
-// fused group; the other inputs are read at (row, col) and every output of
-// the group is stored there.
+// Epilogue inputs 1.. of the fused group at (row, col).
 template <typename T>
-__device__ __forceinline__ void epilogue_apply(const GemmParams &P, double prod, int64_t row,
-                                               int64_t col) {
-    double x[WS_MAX_IN];
-    x[0] = prod;
+__device__ __forceinline__ void epilogue_load(const GemmParams &P, double (&x)[WS_MAX_IN],
+                                              int64_t row, int64_t col) {
 #pragma unroll
     for (int i = 1; i < WS_MAX_IN; ++i)
         if (i < P.nin)
             x[i] = to_f64(static_cast<const T *>(P.ein[i])[row * P.eldi[i] + col]);
+}
+
+// Every output of the fused group at (row, col); x[0] is the reduced product.
+template <typename T>
+__device__ __forceinline__ void epilogue_store(const GemmParams &P, const double (&x)[WS_MAX_IN],
+                                               int64_t row, int64_t col) {
 #pragma unroll
     for (int o = 0; o < WS_MAX_OUT; ++o) {
         if (o >= P.nout)
@@ -201,13 +229,25 @@ __device__ __forceinline__ void epilogue_apply(const GemmParams &P, double prod,
     }
 }
 
+// Epilogue for one element: prod is the reduced product, input 0 of the
+// fused group; the other inputs are read at (row, col) and every output of
+// the group is stored there.
+template <typename T>
+__device__ __forceinline__ void epilogue_apply(const GemmParams &P, double prod, int64_t row,
+                                               int64_t col) {
+    double x[WS_MAX_IN];
+    x[0] = prod;
+    epilogue_load<T>(P, x, row, col);
+    epilogue_store<T>(P, x, row, col);
+}
+
 // ---- LDS-tiled kernel: BM x BN tile per workgroup, four waves in a 2 x 2
 // grid, each wave (BM/2) x (BN/2) of 16 x 16 matrix-core tiles, K-tiles of 16
 // double-buffered through LDS.  In the matrix-core step s of a K-tile, lane l
 // supplies k = 4*(l/16) + s, so each lane's four A values are contiguous in
 // LDS; B uses the same k assignment.
 template <typename T, int BM, int BN, bool CENTRE, bool VEC2>
-__global__ __launch_bounds__(256) void gemm_lds_kernel(GemmParams P) {
+__global__ __launch_bounds__(256, 2) void gemm_lds_kernel(GemmParams P) {
     constexpr int BK = 16, APAD = 2;
     constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
     constexpr int AST = BK + APAD;                       // A row stride in LDS
@@ -387,15 +427,24 @@ __global__ __launch_bounds__(256) void gemm_lds_kernel(GemmParams P) {
     }
 }
 
-// ---- Small products: a 32 x 32 output tile per workgroup, its four waves
-// splitting the K-tiles round-robin, operands read straight from global
-// memory, partial tiles summed through LDS.  This keeps all SIMDs busy when
-// the product has too few output tiles to fill the chip (deep recursion
-// levels).
-template <typename T, bool CENTRE>
-__global__ __launch_bounds__(256) void gemm_sk_kernel(GemmParams P) {
-    constexpr int BM = 32, BN = 32, BK = 16;
-    __shared__ double part[4][BM * BN];
+// ---- Small products: a 32 x 32 output tile per workgroup whose WAVES waves
+// split the K-tiles round-robin (so every SIMD holds two waves even when the
+// product has only a few hundred output tiles).  Operands are read straight
+// from global memory, CH K-tiles of a wave at a time so that all of their
+// loads are in flight together; the epilogue's extra inputs are fetched at
+// kernel start; partial tiles are summed through LDS.
+#ifndef WS_SK_WAVES
+#define WS_SK_WAVES 8   // waves splitting K in the small-product kernel
+#endif
+#ifndef WS_SK_CHUNK
+#define WS_SK_CHUNK 1   // K-tiles per wave whose loads are in flight together
+#endif
+
+template <typename T, bool CENTRE, bool VEC2, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void gemm_sk_kernel(GemmParams P) {
+    constexpr int BM = 32, BN = 32, BK = 16, CH = WS_SK_CHUNK;
+    constexpr int EPT = BM * BN / (64 * WAVES);        // epilogue elements per thread
+    __shared__ double part[WAVES][BM * BN];
     int32_t tm, tn;
     tile_of(P.tiles_m, P.tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
@@ -404,56 +453,96 @@ __global__ __launch_bounds__(256) void gemm_sk_kernel(GemmParams P) {
     const T *A = static_cast<const T *>(P.A);
     const T *B = static_cast<const T *>(P.B);
 
-    f64x4 acc[2][2];
+    // Epilogue inputs do not depend on the product: start fetching them now.
+    double ex[EPT][WS_MAX_IN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-            acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < EPT; ++u) {
+        const int e = tid + 64 * WAVES * u;
+        const int64_t row = m0 + e / BN, col = n0 + e % BN;
+        if (row < P.M && col < P.N)
+            epilogue_load<T>(P, ex[u], row, col);
+    }
 
-    const int64_t ktiles = (P.K + BK - 1) / BK;
-    int since_fold = 0;
-    for (int64_t t = wave; t < ktiles; t += 4) {
+    auto cvt = [&](double x) { return (CENTRE && x > P.half) ? x - P.p : x; };
+    // Operands of K-tile t for this lane: A rows m0 + 16i + li at
+    // k = 16t + 4kq .. +3, B columns n0 + 16j + li at the same k.
+    auto load = [&](int64_t t, double (&af)[2][4], double (&bf)[2][4]) {
         const int64_t k0 = t * BK + 4 * kq;
-        double af[2][4], bf[2][4];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             const int64_t gr = m0 + i * 16 + li;
+            if (VEC2) {
+                double x0 = 0, x1 = 0, x2 = 0, x3 = 0;
+                if (gr < P.M && k0 < P.K) {
+                    const T *src = A + gr * P.lda + k0;
+                    load2(src, x0, x1);
+                    load2(src + 2, x2, x3);
+                }
+                af[i][0] = cvt(x0);
+                af[i][1] = cvt(x1);
+                af[i][2] = cvt(x2);
+                af[i][3] = cvt(x3);
+            } else {
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int64_t gk = k0 + s;
-                af[i][s] = (gr < P.M && gk < P.K)
-                               ? centred(A[gr * P.lda + gk], P.p, P.half, CENTRE) : 0.0;
+                for (int s = 0; s < 4; ++s)
+                    af[i][s] = (gr < P.M && k0 + s < P.K) ? cvt(to_f64(A[gr * P.lda + k0 + s])) : 0.0;
             }
         }
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const int64_t gn = n0 + j * 16 + li;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int64_t gk = k0 + s;
-                bf[j][s] = (gn < P.N && gk < P.K)
-                               ? centred(B[gk * P.ldb + gn], P.p, P.half, CENTRE) : 0.0;
+            for (int s = 0; s < 4; ++s)
+                bf[j][s] = (gn < P.N && k0 + s < P.K) ? cvt(to_f64(B[(k0 + s) * P.ldb + gn])) : 0.0;
+        }
+    };
+
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    int since_fold = 0;
+
+    const int64_t ktiles = (P.K + BK - 1) / BK;
+    double af[CH][2][4], bf[CH][2][4];
+    for (int64_t t0 = wave; t0 < ktiles; t0 += CH * WAVES) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int64_t t = t0 + (int64_t)c * WAVES;
+            if (t < ktiles) {
+                load(t, af[c], bf[c]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        af[c][i][s] = bf[c][i][s] = 0.0;
             }
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+        for (int c = 0; c < CH; ++c) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
-        if (P.kc_tiles > 0 && ++since_fold == P.kc_tiles) {
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[c][i][s], bf[c][j][s], acc[i][j], 0, 0, 0);
+            if (P.kc_tiles > 0 && ++since_fold == P.kc_tiles) {
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        acc[i][j][v] = mod_reduce(acc[i][j][v], P.p, P.pinv);
-            since_fold = 0;
+                    for (int j = 0; j < 2; ++j)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            acc[i][j][v] = mod_reduce(acc[i][j][v], P.p, P.pinv);
+                since_fold = 0;
+            }
         }
     }
+
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -464,13 +553,17 @@ __global__ __launch_bounds__(256) void gemm_sk_kernel(GemmParams P) {
                     mod_reduce(acc[i][j][v], P.p, P.pinv);
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int idx = tid + 256 * e;
-        const int r = idx / BN, c = idx % BN;
-        const double s = part[0][idx] + part[1][idx] + part[2][idx] + part[3][idx];
-        const int64_t row = m0 + r, col = n0 + c;
-        if (row < P.M && col < P.N)
-            epilogue_apply<T>(P, product_residue(P, s), row, col);
+    for (int u = 0; u < EPT; ++u) {
+        const int e = tid + 64 * WAVES * u;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w)
+            s += part[w][e];
+        const int64_t row = m0 + e / BN, col = n0 + e % BN;
+        if (row < P.M && col < P.N) {
+            ex[u][0] = product_residue(P, s);
+            epilogue_store<T>(P, ex[u], row, col);
+        }
     }
 }
 
@@ -518,9 +611,15 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
     } else {
         P.tiles_m = (int32_t)((P.M + 31) / 32);
         P.tiles_n = (int32_t)((P.N + 31) / 32);
-        const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(256);
-        if (centre) hipLaunchKernelGGL((gemm_sk_kernel<T, true>), grid, block, 0, s, P);
-        else hipLaunchKernelGGL((gemm_sk_kernel<T, false>), grid, block, 0, s, P);
+        const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(64 * WS_SK_WAVES);
+        const bool v4 = vec2 && (P.K % 4 == 0);
+        if (centre) {
+            if (v4) hipLaunchKernelGGL((gemm_sk_kernel<T, true, true, WS_SK_WAVES>), grid, block, 0, s, P);
+            else hipLaunchKernelGGL((gemm_sk_kernel<T, true, false, WS_SK_WAVES>), grid, block, 0, s, P);
+        } else {
+            if (v4) hipLaunchKernelGGL((gemm_sk_kernel<T, false, true, WS_SK_WAVES>), grid, block, 0, s, P);
+            else hipLaunchKernelGGL((gemm_sk_kernel<T, false, false, WS_SK_WAVES>), grid, block, 0, s, P);
+        }
     }
     return hipGetLastError();
 }
