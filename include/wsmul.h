@@ -116,6 +116,8 @@ typedef struct ws_stats {
     uint64_t levels;               /* Winograd depth actually used                    */
     int64_t schedule;              /* table actually run (see wsmul_schedule_name)    */
     int64_t base;                  /* base kind actually used                         */
+    uint64_t scratch_bytes;        /* INT8 base: digit planes of the largest base product
+                                      (kernel scratch, not a schedule temporary)       */
 } ws_stats;
 
 /*

@@ -47,7 +47,7 @@ class ws_stats(ctypes.Structure):
                 ("internal_alloc_bytes", _u64), ("add_launches", _u64),
                 ("gemm_launches", _u64), ("element_additions", _u64),
                 ("base_flops", _u64), ("rows", _u64), ("levels", _u64),
-                ("schedule", _i64), ("base", _i64)]
+                ("schedule", _i64), ("base", _i64), ("scratch_bytes", _u64)]
 
 
 class ws_trace(ctypes.Structure):

@@ -1,6 +1,7 @@
 // The C-ABI: argument checks, plan cache, workspace, launch loop, counters.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -103,6 +104,8 @@ int prepare(const ws_args *in, ws_args &a, PlanKey &key, Resolved &res) {
         a.base = WS_BASE_F64_MFMA;
     if (a.base == WS_BASE_I8_LIMBS && !limbs_supported(a.p))
         return fail(WS_EMODULUS, "p too large for three signed 8-bit digits (p <= 16711423)");
+    if (a.base == WS_BASE_I8_LIMBS && a.k > 32768)
+        return fail(WS_ESHAPE, "the 8-bit digit base needs k <= 32768 (exact int32 sums)");
     res = resolve_schedule(a.schedule, a.m, a.k, a.n, beta_nz, a.levels);
     if (res.status != WS_OK)
         return fail(res.status, res.error);
@@ -136,8 +139,9 @@ static void fill_stats(const Plan &plan, const ws_args &a, ws_stats &s) {
 }
 
 // Launch every operation of a plan on `stream`.
-int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, bool trace) {
-    DevBufs bufs{{a.A, a.B, a.C, ws}};
+int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, bool trace,
+             void *scratch, size_t scratch_bytes) {
+    DevBufs bufs{{a.A, a.B, a.C, ws}, scratch, scratch_bytes};
     std::vector<hipEvent_t> ev;
     if (trace) {
         ev.resize(plan.ops.size() + 1);
@@ -219,11 +223,29 @@ int execute(const ws_args &a, const PlanKey &key) {
             return rc;
         }
     }
-    const int rc = run_plan(*plan, a, ws, stream, (a.flags & WS_FLAG_TRACE) != 0);
+    // Digit planes for the INT8 base: sized for the largest base product.
+    size_t scratch_bytes = 0;
+    void *scratch = nullptr;
+    if (a.base == WS_BASE_I8_LIMBS) {
+        for (const OpDesc &op : plan->ops)
+            if (op.kind == WS_OP_GEMM)
+                scratch_bytes = std::max(scratch_bytes,
+                                         digit_scratch_bytes(op.a.rows, op.b.cols, op.a.cols));
+        if (scratch_bytes && hipMallocAsync(&scratch, scratch_bytes, stream) != hipSuccess) {
+            if (owned)
+                (void)hipFreeAsync(ws, stream);
+            return fail(WS_ENOMEM, "digit scratch allocation failed");
+        }
+    }
+    const int rc = run_plan(*plan, a, ws, stream, (a.flags & WS_FLAG_TRACE) != 0, scratch,
+                            scratch_bytes);
+    if (scratch)
+        (void)hipFreeAsync(scratch, stream);
     if (owned)
         (void)hipFreeAsync(ws, stream);
     fill_stats(*plan, a, g_stats);
-    g_stats.internal_alloc_bytes = owned ? ws_bytes : 0;
+    g_stats.internal_alloc_bytes = (owned ? ws_bytes : 0) + scratch_bytes;
+    g_stats.scratch_bytes = scratch_bytes;
     if (g_stats.workspace_bytes > g_stats.peak_temp_bytes)
         g_stats.peak_temp_bytes = g_stats.workspace_bytes;
     return rc;

@@ -10,6 +10,8 @@ namespace wsmul {
 // Base pointers of the four buffers a plan refers to (WS_BUF_A .. WS_BUF_W).
 struct DevBufs {
     void *ptr[4];
+    void *scratch;          // digit planes of the INT8 base (WS_BASE_I8_LIMBS)
+    size_t scratch_bytes;
 };
 
 // One fused group of addition rows (elementwise, HBM-bound).

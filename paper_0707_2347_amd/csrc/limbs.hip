@@ -1,14 +1,324 @@
-// Base products from signed 8-bit digits of centred residues (INT8 matrix cores).
+// Base products from signed 8-bit digits of centred residues on the INT8
+// matrix cores (v_mfma_i32_16x16x64_i8).
+//
+// A residue x in [0, p) is centred (c = x - p when x > (p-1)/2) and written
+// in balanced base 256: c = d0 + 2^8 d1 + 2^16 d2 with every digit in
+// [-128, 127] (enough for p <= 16,711,423).  The product becomes
+//     A*B = sum_{w=0..4} 2^(8w) * sum_{i+j=w} A_i * B_j,
+// where every digit product is exact in int32: a weight class holds at most
+// three digit products of magnitude <= K * 2^14, below 2^31 for K <= 32768.
+// The epilogue reduces each class mod p, recombines with the residues
+// 2^(8w) mod p, applies alpha and runs the fused addition rows.
+//
+// Digits are first written to a scratch area as three int8 planes per
+// operand, each R x Kp with the inner dimension contiguous (B transposed),
+// rows padded to the 128-row tile and Kp to the 64-wide K-step with zeros.
+#include "gemm_common.hpp"
 #include "wsmul_internal.hpp"
 
 namespace wsmul {
 
 bool limbs_supported(int64_t p) { return p <= 16711423; }
 
+namespace {
+
+constexpr int TILE = 128;     // output tile per workgroup (both dimensions)
+constexpr int KSTEP = 64;     // inner dimension per matrix-core op
+constexpr int ROWB = 80;      // LDS bytes per digit row (64 + 16: no bank conflicts)
+
+int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+__device__ __forceinline__ void digits3(double x, double p, double half, int8_t &d0, int8_t &d1,
+                                        int8_t &d2) {
+    const int32_t c = (int32_t)(x > half ? x - p : x);
+    const int32_t e0 = ((c + 128) & 255) - 128;
+    const int32_t c1 = (c - e0) >> 8;
+    const int32_t e1 = ((c1 + 128) & 255) - 128;
+    const int32_t c2 = (c1 - e1) >> 8;
+    d0 = (int8_t)e0;
+    d1 = (int8_t)e1;
+    d2 = (int8_t)c2;
+}
+
+// A (R x K, row-major) -> planes[d][r][k]; 8 consecutive k per thread.
+template <typename T>
+__global__ __launch_bounds__(256) void split_rows_kernel(const T *X, int64_t ld, int64_t R,
+                                                         int64_t K, int64_t Rp, int64_t Kp,
+                                                         int8_t *planes, double p, double half) {
+    const int64_t per_row = Kp / 8;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= Rp * per_row)
+        return;
+    const int64_t r = idx / per_row, k0 = (idx % per_row) * 8;
+    union {
+        int8_t b[8];
+        uint64_t u;
+    } o0, o1, o2;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int64_t k = k0 + t;
+        const double x = (r < R && k < K) ? to_f64(X[r * ld + k]) : 0.0;
+        digits3(x, p, half, o0.b[t], o1.b[t], o2.b[t]);
+    }
+    const int64_t plane = Rp * Kp;
+    *reinterpret_cast<uint64_t *>(planes + r * Kp + k0) = o0.u;
+    *reinterpret_cast<uint64_t *>(planes + plane + r * Kp + k0) = o1.u;
+    *reinterpret_cast<uint64_t *>(planes + 2 * plane + r * Kp + k0) = o2.u;
+}
+
+// B (K x N, row-major) -> planes[d][n][k] (transposed through LDS in 64 x 64
+// tiles so that both the reads and the writes are contiguous).
+template <typename T>
+__global__ __launch_bounds__(256) void split_cols_kernel(const T *X, int64_t ld, int64_t K,
+                                                         int64_t N, int64_t Np, int64_t Kp,
+                                                         int8_t *planes, double p, double half) {
+    __shared__ __attribute__((aligned(16))) int8_t tile[3][64][64 + 16];
+    const int64_t k0 = (int64_t)blockIdx.x * 64, n0 = (int64_t)blockIdx.y * 64;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int e = tid + 256 * t;
+        const int kk = e / 64, nn = e % 64;
+        const int64_t k = k0 + kk, n = n0 + nn;
+        const double x = (k < K && n < N) ? to_f64(X[k * ld + n]) : 0.0;
+        int8_t d0, d1, d2;
+        digits3(x, p, half, d0, d1, d2);
+        tile[0][nn][kk] = d0;
+        tile[1][nn][kk] = d1;
+        tile[2][nn][kk] = d2;
+    }
+    __syncthreads();
+    const int64_t plane = Np * Kp;
+    // 3 digits x 64 rows x 64 bytes = 768 chunks of 16 bytes.
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        const int q = tid + 256 * t;
+        const int d = q / 256, nn = (q % 256) / 4, part = q % 4;
+        const int64_t n = n0 + nn;
+        if (n < Np && k0 + 16 * part < Kp) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(&tile[d][nn][16 * part]);
+            *reinterpret_cast<uint4 *>(planes + d * plane + n * Kp + k0 + 16 * part) = v;
+        }
+    }
+}
+
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
+struct DigitParams {
+    GemmParams g;              // shapes, modulus, alpha and the fused epilogue
+    const int8_t *Ad;          // 3 planes, Mp x Kp
+    const int8_t *Bd;          // 3 planes, Np x Kp
+    int64_t Mp, Np, Kp;
+    double cw[5];              // 2^(8w) mod p
+};
+
+// 128 x 128 output tile, four waves in a 2 x 2 grid (64 x 64 each, one wave
+// per SIMD so that the five int32 accumulator sets -- one per weight class,
+// 320 registers -- fit without spilling), digit tiles of 64 inner elements
+// double-buffered through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_digits_kernel(DigitParams D) {
+    __shared__ __attribute__((aligned(16))) int8_t lds[2][2][3][TILE * ROWB];   // [stage][A|B][digit][row*ROWB]
+    const GemmParams &P = D.g;
+    int32_t tm, tn;
+    tile_of(P.tiles_m, P.tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * TILE, n0 = (int64_t)tn * TILE;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;       // 2 x 2 waves
+    const int li = lane & 15, g = lane >> 4;
+    const int64_t plA = D.Mp * D.Kp, plB = D.Np * D.Kp;
+
+    // Staging: A and B each 3 digits x 128 rows x 64 bytes = 1536 chunks of
+    // 16 bytes, i.e. six of each per thread, moved in three groups (two of A
+    // and two of B each) interleaved with the three digit rounds of the
+    // matrix-core loop, so that only one group occupies registers at a time.
+    constexpr int CPT = 3 * TILE * KSTEP / 16 / 256;
+    static_assert(CPT == 6, "three groups of two chunks");
+    uint4 sa[2], sb[2];
+    auto gload = [&](int grp, int64_t k0) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = tid + 256 * (2 * grp + j);
+            const int d = q / (TILE * 4), row = (q % (TILE * 4)) / 4, part = q % 4;
+            sa[j] = *reinterpret_cast<const uint4 *>(D.Ad + d * plA + (m0 + row) * D.Kp + k0 + 16 * part);
+            sb[j] = *reinterpret_cast<const uint4 *>(D.Bd + d * plB + (n0 + row) * D.Kp + k0 + 16 * part);
+        }
+    };
+    auto sstore = [&](int grp, int st) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int q = tid + 256 * (2 * grp + j);
+            const int d = q / (TILE * 4), row = (q % (TILE * 4)) / 4, part = q % 4;
+            *reinterpret_cast<uint4 *>(&lds[st][0][d][row * ROWB + 16 * part]) = sa[j];
+            *reinterpret_cast<uint4 *>(&lds[st][1][d][row * ROWB + 16 * part]) = sb[j];
+        }
+    };
+
+    i32x4 acc[5][4][4];
+#pragma unroll
+    for (int w = 0; w < 5; ++w)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[w][i][j] = i32x4{0, 0, 0, 0};
+
+    const int64_t ksteps = D.Kp / KSTEP;
+    if (ksteps > 0) {
+#pragma unroll
+        for (int grp = 0; grp < 3; ++grp) {
+            gload(grp, 0);
+            sstore(grp, 0);
+        }
+    }
+    __syncthreads();
+    for (int64_t t = 0; t < ksteps; ++t) {
+        const int cur = (int)(t & 1);
+        const bool more = t + 1 < ksteps;
+        // B fragments of digit b stay in registers while the A fragments of
+        // each digit a are read from LDS for the (a, b) pair.
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if (more)
+                gload(b, (t + 1) * KSTEP);
+            i32x4 bf[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bf[j] = *reinterpret_cast<const i32x4 *>(
+                    &lds[cur][1][b][(wn * 64 + j * 16 + li) * ROWB + 16 * g]);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                i32x4 af[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    af[i] = *reinterpret_cast<const i32x4 *>(
+                        &lds[cur][0][a][(wm * 64 + i * 16 + li) * ROWB + 16 * g]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[a + b][i][j] =
+                            __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[j], acc[a + b][i][j], 0, 0, 0);
+            }
+            if (more)
+                sstore(b, cur ^ 1);
+        }
+        __syncthreads();
+    }
+
+    // Recombine the weight classes into residues, apply alpha, stage through
+    // LDS (two rounds of 64 rows, one per wave row) and run the fused epilogue
+    // on whole rows.  Output layout of the 16 x 16 x 64 int8 op: lane l,
+    // element v holds row 4*(l/16) + v of column l % 16.
+    double *stage = reinterpret_cast<double *>(&lds[0][0][0][0]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (wm == h) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        double s = 0.0;
+#pragma unroll
+                        for (int w = 0; w < 5; ++w)
+                            s = fma(D.cw[w], mod_reduce((double)acc[w][i][j][v], P.p, P.pinv), s);
+                        const int r = i * 16 + 4 * g + v;
+                        stage[r * TILE + wn * 64 + j * 16 + li] = product_residue(P, s);
+                    }
+        }
+        __syncthreads();
+        for (int e = tid; e < 64 * TILE; e += 256) {
+            const int r = e / TILE, c = e % TILE;
+            const int64_t row = m0 + h * 64 + r, col = n0 + c;
+            if (row < P.M && col < P.N)
+                epilogue_apply<T>(P, stage[e], row, col);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+size_t digit_scratch_bytes(int64_t M, int64_t N, int64_t K) {
+    const int64_t Kp = round_up(std::max<int64_t>(K, 1), KSTEP);
+    return (size_t)(3 * (round_up(M, TILE) + round_up(N, TILE)) * Kp);
+}
+
 hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtype, int64_t p,
                              hipStream_t stream) {
-    (void)op; (void)bufs; (void)dtype; (void)p; (void)stream;
-    return hipErrorNotSupported;
+    const int64_t M = op.a.rows, K = op.a.cols, N = op.b.cols;
+    if (M == 0 || N == 0)
+        return hipSuccess;
+    if (K > 32768 || !limbs_supported(p))
+        return hipErrorInvalidValue;
+    if (!bufs.scratch || bufs.scratch_bytes < digit_scratch_bytes(M, N, K))
+        return hipErrorInvalidValue;
+    const size_t esz = 8;
+    DigitParams D{};
+    GemmParams &P = D.g;
+    P.M = M;
+    P.N = N;
+    P.K = K;
+    P.p = (double)p;
+    P.pinv = 1.0 / (double)p;
+    P.half = std::floor((double)p / 2.0);
+    P.alpha = (double)op.alpha;
+    P.nin = op.nin;
+    P.nout = op.nout;
+    for (int i = 1; i < op.nin; ++i) {
+        P.ein[i] = static_cast<const char *>(bufs.ptr[op.in[i].buf]) + op.in[i].off * esz;
+        P.eldi[i] = op.in[i].ld;
+    }
+    for (int o = 0; o < op.nout; ++o) {
+        P.eout[o] = static_cast<char *>(bufs.ptr[op.out[o].buf]) + op.out[o].off * esz;
+        P.eldo[o] = op.out[o].ld;
+        for (int i = 0; i < op.nin; ++i)
+            P.coef[o][i] = (double)op.coef[o][i];
+    }
+    D.Mp = round_up(M, TILE);
+    D.Np = round_up(N, TILE);
+    D.Kp = round_up(std::max<int64_t>(K, 1), KSTEP);
+    int8_t *Ad = static_cast<int8_t *>(bufs.scratch);
+    int8_t *Bd = Ad + 3 * D.Mp * D.Kp;
+    D.Ad = Ad;
+    D.Bd = Bd;
+    int64_t pw = 1;
+    for (int w = 0; w < 5; ++w) {
+        D.cw[w] = (double)pw;
+        pw = (pw * 256) % p;
+    }
+    const void *Aop = static_cast<const char *>(bufs.ptr[op.a.buf]) + op.a.off * esz;
+    const void *Bop = static_cast<const char *>(bufs.ptr[op.b.buf]) + op.b.off * esz;
+    const uint32_t blocks_a = (uint32_t)((D.Mp * (D.Kp / 8) + 255) / 256);
+    const dim3 grid_b((uint32_t)(D.Kp / 64), (uint32_t)(D.Np / 64));
+    if (dtype == WS_I64) {
+        hipLaunchKernelGGL(split_rows_kernel<int64_t>, dim3(blocks_a), dim3(256), 0, stream,
+                           static_cast<const int64_t *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
+                           P.p, P.half);
+        hipLaunchKernelGGL(split_cols_kernel<int64_t>, grid_b, dim3(256), 0, stream,
+                           static_cast<const int64_t *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
+                           P.p, P.half);
+    } else {
+        hipLaunchKernelGGL(split_rows_kernel<double>, dim3(blocks_a), dim3(256), 0, stream,
+                           static_cast<const double *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
+                           P.p, P.half);
+        hipLaunchKernelGGL(split_cols_kernel<double>, grid_b, dim3(256), 0, stream,
+                           static_cast<const double *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
+                           P.p, P.half);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    P.tiles_m = (int32_t)(D.Mp / TILE);
+    P.tiles_n = (int32_t)(D.Np / TILE);
+    const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(256);
+    if (dtype == WS_I64)
+        hipLaunchKernelGGL(gemm_digits_kernel<int64_t>, grid, block, 0, stream, D);
+    else
+        hipLaunchKernelGGL(gemm_digits_kernel<double>, grid, block, 0, stream, D);
+    return hipGetLastError();
 }
 
 }  // namespace wsmul

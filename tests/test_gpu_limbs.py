@@ -1,0 +1,74 @@
+"""GPU parity of the 8-bit digit base (centred residues, balanced base-256
+digits, int32 matrix-core sums, recombination mod p) against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import ref
+from oracle.schedules import replay
+from paper_0707_2347_amd import capi, inputs
+
+from .gpu_util import call
+
+pytestmark = pytest.mark.gpu
+I8 = capi.WS_BASE_I8_LIMBS
+
+
+@pytest.mark.parametrize("dtype", [capi.WS_F64, capi.WS_I64])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (16, 64, 16), (17, 33, 9), (100, 257, 130),
+                                   (128, 64, 128), (300, 200, 700), (129, 1000, 255),
+                                   (1024, 1024, 1024), (4, 0, 6)])
+@pytest.mark.parametrize("p", [3, 251, 65521, 1048573, 8388593, 16711421])
+def test_digit_base_classical(shape, dtype, p):
+    m, k, n = shape
+    print("digits", shape, dtype, p, flush=True)
+    A, B, C = inputs.uniform(m * 31 + k * 3 + n + p % 97, m, k, n, p, with_c=True)
+    for alpha, beta in [(1, 0), (p - 1, 3 % p)]:
+        st, C2, _, _ = call(capi.WS_CLASSICAL, A, B, C, alpha, beta, p, 0, dtype=dtype, base=I8)
+        assert st == capi.WS_OK, capi.wsmul_last_error()
+        assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, alpha, beta, p)), (alpha, beta)
+
+
+@pytest.mark.parametrize("p", [65521, 1048573, 8388593, 16711421])
+def test_digit_extremes(p):
+    """Residues whose centred value has the largest digits, long K."""
+    m, k, n = 64, 4096, 48
+    h = (p - 1) // 2
+    rng = np.random.default_rng(p)
+    choices = np.array([h, h + 1, p - 1, 1, 0], dtype=np.int64)
+    A = choices[rng.integers(0, 5, size=(m, k))]
+    B = choices[rng.integers(0, 5, size=(k, n))]
+    st, C2, _, _ = call(capi.WS_CLASSICAL, A, B, None, 1, 0, p, 0, base=I8)
+    assert st == capi.WS_OK
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, None, 1, 0, p))
+    A[:] = h
+    B[:] = h + 1
+    st, C2, _, _ = call(capi.WS_CLASSICAL, A, B, None, 1, 0, p, 0, base=I8)
+    assert np.all(C2 == (k * h * (h + 1)) % p)
+
+
+@pytest.mark.parametrize("schedule,shape,levels,acc", [
+    (capi.WS_TWO_TEMP, (256, 256, 256), 2, False), (capi.WS_TWO_TEMP, (256, 256, 256), 2, True),
+    (capi.WS_OVERWRITE, (256, 256, 256), 2, True), (capi.WS_READONLY_INPLACE, (256, 128, 256), 2, False),
+    (capi.WS_TWO_TEMP, (300, 260, 190), 1, False)])
+def test_digit_base_schedules(schedule, shape, levels, acc):
+    m, k, n = shape
+    p = 1048573
+    A, B, C = inputs.uniform(99 + levels, m, k, n, p, with_c=True)
+    beta = 5 if acc else 0
+    st, C2, A2, B2 = call(schedule, A, B, C, 3, beta, p, levels, base=I8)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, 3, beta, p))
+    if schedule == capi.WS_OVERWRITE:
+        r = replay("aclr", A, B, C, 3, beta, p, levels)
+        assert np.array_equal(A2, r.A) and np.array_equal(B2, r.B)
+    s = capi.wsmul_get_stats()
+    assert s.base == I8 and s.scratch_bytes > 0
+
+
+def test_digit_base_limits():
+    import torch
+    d = torch.zeros(4, dtype=torch.float64, device="cuda:0")
+    a = capi.make_args(1, 40000, 1, 65521, d, d, d, 1, 0, capi.WS_CLASSICAL, 0, base=I8)
+    assert capi.wsmul_mod_p_ex(a) == capi.WS_ESHAPE
+    a = capi.make_args(1, 1, 1, 16711433, d, d, d, 1, 0, capi.WS_CLASSICAL, 0, base=I8)
+    assert capi.wsmul_mod_p_ex(a) == capi.WS_EMODULUS
