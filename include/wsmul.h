@@ -83,7 +83,8 @@ typedef enum {
 enum {
     WS_FLAG_CHECK = 1u << 0,   /* verify every entry lies in [0, p) first (WS_ERANGE) */
     WS_FLAG_NOFUSE = 1u << 1,  /* one launch per schedule row (no row fusion)         */
-    WS_FLAG_TRACE = 1u << 2    /* time every launch with events (wsmul_get_trace)     */
+    WS_FLAG_TRACE = 1u << 2,   /* time every launch with events (wsmul_get_trace)     */
+    WS_FLAG_SYNC = 1u << 3     /* wsmul_batched: wait for completion, report errors   */
 };
 
 /* Full argument block.  Zero lda/ldb/ldc mean dense (k, n, n). */
@@ -118,6 +119,7 @@ typedef struct ws_stats {
     int64_t base;                  /* base kind actually used                         */
     uint64_t scratch_bytes;        /* INT8 base: digit planes of the largest base product
                                       (kernel scratch, not a schedule temporary)       */
+    uint64_t batch_phases;         /* batches: persistent launches (phases) issued     */
 } ws_stats;
 
 /*
@@ -170,6 +172,42 @@ WSMUL_API int wsmul_reset_stats(void);
 WSMUL_API const char *wsmul_last_error(void);
 WSMUL_API const char *wsmul_schedule_name(int table_id);
 WSMUL_API const char *wsmul_version(void);
+
+/* ------------------------------------------------------------------------
+ * Batches.  Many independent products (binary64 storage and base), each with
+ * its own shape, modulus and schedule (WS_AUTO and levels = -1 allowed).
+ * Operation j of every product forms phase j; the operations of a phase are
+ * independent, so each phase is ONE persistent launch whose workgroups walk
+ * its tasks -- one 64 x 64 output tile of a base product or one chunk of an
+ * addition group -- round-robin, with no atomics and no waiting.  A batch of
+ * single-operation products (classical products, which the autotuner picks
+ * for sizes up to 2048) is therefore one launch.  All products' temporaries
+ * are live at once: the call needs the sum of their workspaces (attached
+ * with wsmul_set_workspace, else allocated stream-ordered), reported in
+ * ws_stats.workspace_bytes.  The stream is probs[0].stream.  With
+ * WS_FLAG_SYNC the call waits for completion and reports HIP errors.
+ */
+WSMUL_API int wsmul_batched(const ws_args *probs, int count, unsigned flags);
+
+/* The same batch captured once into a hipGraph (one persistent launch per
+ * phase) with its device state; *graph_exec receives an opaque handle.
+ * Pointers in probs are baked in: replays recompute the same products from
+ * whatever A, B, C then hold. */
+WSMUL_API int wsmul_graph_capture(const ws_args *probs, int count, void **graph_exec);
+WSMUL_API int wsmul_graph_launch(void *graph_exec, void *stream);
+/* Wait for the stream; WS_EHIP if a HIP error was raised. */
+WSMUL_API int wsmul_graph_check(void *graph_exec, void *stream);
+WSMUL_API int wsmul_graph_destroy(void *graph_exec);
+
+/* Choose schedule, Winograd depth and base for one product: every candidate
+ * whose temporaries fit mem_budget is expanded into its fused plan and costed
+ * with per-kernel rates measured on MI355X (base products by tile class and
+ * base kind, addition groups by bytes moved, a floor per launch).  Fills
+ * choice->schedule, ->levels, ->base; other fields are left as passed.
+ * Decisions are cached in memory and, when WSMUL_TUNE_CACHE names a file, in
+ * that file (one JSON object per line). */
+WSMUL_API int wsmul_autotune(int64_t m, int64_t k, int64_t n, int64_t p, int dtype,
+                             size_t mem_budget, ws_args *choice);
 
 /* ------------------------------------------------------------------------
  * Plan introspection (host only, no GPU needed).

@@ -19,7 +19,7 @@ WS_OK, WS_EINVAL, WS_ESHAPE, WS_EMODULUS, WS_ERANGE, WS_ESCHEDULE, WS_ENOMEM, WS
  WS_OVR, WS_ACCR) = range(8)
 WS_F64, WS_I64 = 0, 1
 WS_BASE_AUTO, WS_BASE_F64_MFMA, WS_BASE_I8_LIMBS = 0, 1, 2
-WS_FLAG_CHECK, WS_FLAG_NOFUSE, WS_FLAG_TRACE = 1, 2, 4
+WS_FLAG_CHECK, WS_FLAG_NOFUSE, WS_FLAG_TRACE, WS_FLAG_SYNC = 1, 2, 4, 8
 WS_MAX_IN, WS_MAX_OUT = 8, 6
 WS_BUF_A, WS_BUF_B, WS_BUF_C, WS_BUF_W = 0, 1, 2, 3
 WS_OP_ADD, WS_OP_GEMM = 0, 1
@@ -47,7 +47,8 @@ class ws_stats(ctypes.Structure):
                 ("internal_alloc_bytes", _u64), ("add_launches", _u64),
                 ("gemm_launches", _u64), ("element_additions", _u64),
                 ("base_flops", _u64), ("rows", _u64), ("levels", _u64),
-                ("schedule", _i64), ("base", _i64), ("scratch_bytes", _u64)]
+                ("schedule", _i64), ("base", _i64), ("scratch_bytes", _u64),
+                ("batch_phases", _u64)]
 
 
 class ws_trace(ctypes.Structure):
@@ -101,15 +102,17 @@ def lib():
                                                  ctypes.POINTER(ws_op_desc), _i64,
                                                  ctypes.POINTER(_i64)]),
         }
-        optional = {
+        optional = {}
+        sig.update({
             "wsmul_batched": (ctypes.c_int, [ctypes.POINTER(ws_args), ctypes.c_int, _u32]),
             "wsmul_graph_capture": (ctypes.c_int, [ctypes.POINTER(ws_args), ctypes.c_int,
                                                    ctypes.POINTER(_vp)]),
             "wsmul_graph_launch": (ctypes.c_int, [_vp, _vp]),
+            "wsmul_graph_check": (ctypes.c_int, [_vp, _vp]),
             "wsmul_graph_destroy": (ctypes.c_int, [_vp]),
             "wsmul_autotune": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int,
                                               ctypes.c_size_t, ctypes.POINTER(ws_args)]),
-        }
+        })
         for name, (res, args) in sig.items():
             f = getattr(L, name)
             f.restype, f.argtypes = res, args
@@ -227,3 +230,36 @@ def wsmul_plan_export(args):
     ops = (ws_op_desc * max(cnt.value, 1))()
     check(lib().wsmul_plan_export(ctypes.byref(args), ops, cnt.value, ctypes.byref(cnt)))
     return list(ops)[:cnt.value]
+
+
+def wsmul_batched(args_list, flags=0):
+    arr = (ws_args * max(len(args_list), 1))(*args_list)
+    return lib().wsmul_batched(arr, len(args_list), flags)
+
+
+def wsmul_graph_capture(args_list):
+    arr = (ws_args * max(len(args_list), 1))(*args_list)
+    h = _vp()
+    st = lib().wsmul_graph_capture(arr, len(args_list), ctypes.byref(h))
+    return st, h.value
+
+
+def wsmul_graph_launch(handle, stream=None):
+    return lib().wsmul_graph_launch(handle, _stream(stream))
+
+
+def wsmul_graph_check(handle, stream=None):
+    return lib().wsmul_graph_check(handle, _stream(stream))
+
+
+def wsmul_graph_destroy(handle):
+    return lib().wsmul_graph_destroy(handle)
+
+
+def wsmul_autotune(m, k, n, p, dtype=WS_F64, mem_budget=(1 << 64) - 1, schedule=WS_AUTO,
+                   levels=-1, base=WS_BASE_AUTO, beta=0):
+    """Return (status, schedule, levels, base) chosen for one product."""
+    c = ws_args()
+    c.schedule, c.levels, c.base, c.beta = schedule, levels, base, beta
+    st = lib().wsmul_autotune(m, k, n, p, dtype, mem_budget, ctypes.byref(c))
+    return st, c.schedule, c.levels, c.base

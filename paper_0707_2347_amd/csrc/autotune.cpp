@@ -1,22 +1,275 @@
-// Choice of schedule, Winograd depth and base kind.
+// Choice of schedule, Winograd depth and base kind per product.
+//
+// Every admissible candidate is expanded into its real fused plan (the plan
+// cache keeps this cheap) and costed operation by operation with rates
+// measured on MI355X for the kernels of this library:
+//   base products, binary64 matrix cores: 58 TFLOP/s for the 128 x 128 tile
+//     class (x0.87 when the accumulators must be folded), 30 TFLOP/s for the
+//     64 x 64 class, 19 TFLOP/s for the split-K class, 8 us floor per launch;
+//   base products, 8-bit digits: 96 / 83 / 65 / 30 TFLOP/s (equivalent) by
+//     tile count, plus the digit split passes (bytes at 5 TB/s);
+//   addition groups: bytes moved at 4.5 TB/s, 4 us floor per launch.
+// The cheapest candidate whose temporaries fit the memory budget wins.
+// Overwriting schedules are never chosen automatically (they destroy A, B).
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "wsmul_internal.hpp"
 
 namespace wsmul {
 
-int autotune_choice(ws_args &a, bool beta_nonzero) {
-    if (a.schedule == WS_AUTO)
-        a.schedule = WS_TWO_TEMP;
-    if (a.levels < 0) {
-        int64_t s = std::min(a.m, std::min(a.k, a.n));
-        int l = 0;
-        while (s >= 4096 && l < 4) {
-            s /= 2;
-            ++l;
-        }
-        a.levels = l;
+namespace {
+
+double gemm_f64_us(int64_t M, int64_t N, int64_t K, int64_t p) {
+    const double flops = 2.0 * (double)M * (double)N * (double)K;
+    const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
+    const int64_t mid = ((M + 63) / 64) * ((N + 63) / 64);
+    double rate = big >= 512 ? 58e12 : (mid >= 256 ? 30e12 : 19e12);
+    const double per_tile = 16.0 * (double)(p - 1) * (double)(p - 1);
+    if (per_tile * ((double)K / 16.0 + 1.0) >= 9.0e15)
+        rate *= 0.87;   // accumulators folded back to residues during the loop
+    return std::max(8.0, flops / rate * 1e6);
+}
+
+double gemm_digits_us(int64_t M, int64_t N, int64_t K) {
+    const double flops = 2.0 * (double)M * (double)N * (double)K;
+    const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
+    const double rate = tiles >= 1024 ? 96e12 : (tiles >= 256 ? 83e12 : (tiles >= 64 ? 65e12 : 30e12));
+    const double split_bytes = 11.0 * ((double)M * (double)K + (double)K * (double)N);
+    return std::max(8.0, flops / rate * 1e6) + 2.0 * 5.0 + split_bytes / 5e12 * 1e6;
+}
+
+struct Key {
+    int64_t m, k, n, p;
+    int dtype, beta_nz, schedule, levels, base;
+    size_t budget;
+    bool operator<(const Key &o) const {
+        return std::tie(m, k, n, p, dtype, beta_nz, schedule, levels, base, budget) <
+               std::tie(o.m, o.k, o.n, o.p, o.dtype, o.beta_nz, o.schedule, o.levels, o.base, o.budget);
     }
+};
+struct Choice {
+    int schedule, levels, base;
+    double cost_us;
+};
+
+std::mutex g_tune_mu;
+std::map<Key, Choice> g_tune;
+bool g_loaded = false;
+
+const char *cache_path() { return std::getenv("WSMUL_TUNE_CACHE"); }
+
+void load_cache() {
+    if (g_loaded)
+        return;
+    g_loaded = true;
+    const char *path = cache_path();
+    if (!path)
+        return;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        Key k{};
+        Choice c{};
+        long long m, kk, n, p;
+        unsigned long long budget;
+        if (std::sscanf(line,
+                        "{\"m\": %lld, \"k\": %lld, \"n\": %lld, \"p\": %lld, \"dtype\": %d, "
+                        "\"beta_nz\": %d, \"schedule_in\": %d, \"levels_in\": %d, \"base_in\": %d, "
+                        "\"budget\": %llu, \"schedule\": %d, \"levels\": %d, \"base\": %d, "
+                        "\"cost_us\": %lf}",
+                        &m, &kk, &n, &p, &k.dtype, &k.beta_nz, &k.schedule, &k.levels, &k.base,
+                        &budget, &c.schedule, &c.levels, &c.base, &c.cost_us) == 14) {
+            k.m = m;
+            k.k = kk;
+            k.n = n;
+            k.p = p;
+            k.budget = (size_t)budget;
+            g_tune[k] = c;
+        }
+    }
+    std::fclose(f);
+}
+
+void save_entry(const Key &k, const Choice &c) {
+    const char *path = cache_path();
+    if (!path)
+        return;
+    FILE *f = std::fopen(path, "a");
+    if (!f)
+        return;
+    std::fprintf(f,
+                 "{\"m\": %lld, \"k\": %lld, \"n\": %lld, \"p\": %lld, \"dtype\": %d, "
+                 "\"beta_nz\": %d, \"schedule_in\": %d, \"levels_in\": %d, \"base_in\": %d, "
+                 "\"budget\": %llu, \"schedule\": %d, \"levels\": %d, \"base\": %d, "
+                 "\"cost_us\": %.3f}\n",
+                 (long long)k.m, (long long)k.k, (long long)k.n, (long long)k.p, k.dtype, k.beta_nz,
+                 k.schedule, k.levels, k.base, (unsigned long long)k.budget, c.schedule, c.levels,
+                 c.base, c.cost_us);
+    std::fclose(f);
+}
+
+// Search every admissible candidate; returns false if none fits.
+bool search(const Key &key, Choice &best) {
+    bool found = false;
+    best.cost_us = 1e300;
+    const int64_t mn = std::min(key.m, std::min(key.k, key.n));
+    int max_l = 0;
+    while (max_l < 5 && (mn >> (max_l + 1)) >= 64)
+        ++max_l;
+    std::vector<int> schedules;
+    if (key.schedule != WS_AUTO)
+        schedules.push_back(key.schedule);
+    else {
+        // Read-only candidates: classical, the two-temporary schedules
+        // (Table 1 / Table 9), Algorithm 2 for C = A*B, and Table 2 for
+        // accumulating products that Table 9 cannot take (non-square).
+        schedules.push_back(WS_CLASSICAL);
+        schedules.push_back(WS_TWO_TEMP);
+        if (!key.beta_nz)
+            schedules.push_back(WS_READONLY_INPLACE);
+        else
+            schedules.push_back(WS_HL_THREE_TEMP);
+    }
+    std::vector<int> bases;
+    if (key.base != WS_BASE_AUTO)
+        bases.push_back(key.base);
+    else {
+        bases.push_back(WS_BASE_F64_MFMA);
+        if (limbs_supported(key.p) && key.k <= 32768 && key.k > 0)
+            bases.push_back(WS_BASE_I8_LIMBS);
+    }
+    for (int sched : schedules) {
+        const int lo = key.levels >= 0 ? key.levels : (sched == WS_CLASSICAL ? 0 : 1);
+        const int hi = key.levels >= 0 ? key.levels : (sched == WS_CLASSICAL ? 0 : max_l);
+        for (int l = lo; l <= hi; ++l) {
+            const Resolved r = resolve_schedule(sched, key.m, key.k, key.n, key.beta_nz != 0, l);
+            if (r.status != WS_OK)
+                continue;
+            PlanKey pk{};
+            pk.m = key.m;
+            pk.k = key.k;
+            pk.n = key.n;
+            pk.p = key.p;
+            pk.lda = key.k;
+            pk.ldb = key.n;
+            pk.ldc = key.n;
+            pk.alpha = 1;
+            pk.beta = key.beta_nz ? 1 : 0;
+            pk.dtype = key.dtype;
+            pk.table = r.table;
+            pk.levels = r.levels;
+            pk.fuse = 1;
+            std::shared_ptr<Plan> plan;
+            try {
+                plan = get_plan(pk);
+            } catch (...) {
+                continue;
+            }
+            if ((size_t)plan->ws_elems * 8u > key.budget)
+                continue;
+            for (int base : bases) {
+                const double c = plan_cost_us(*plan, base);
+                if (c < best.cost_us) {
+                    best = Choice{sched, l, base, c};
+                    found = true;
+                }
+            }
+        }
+    }
+    return found;
+}
+
+}  // namespace
+
+double plan_cost_us(const Plan &plan, int base) {
+    double t = 0.0;
+    for (const OpDesc &op : plan.ops) {
+        if (op.kind == WS_OP_GEMM) {
+            t += base == WS_BASE_I8_LIMBS ? gemm_digits_us(op.a.rows, op.b.cols, op.a.cols)
+                                          : gemm_f64_us(op.a.rows, op.b.cols, op.a.cols, plan.key.p);
+            t += 8.0 * (double)(op.nin - 1 + op.nout) * (double)op.out[0].rows *
+                 (double)op.out[0].cols / 4.5e12 * 1e6;   // epilogue traffic
+        } else {
+            const double bytes = 8.0 * (double)(op.nin + op.nout) * (double)op.out[0].rows *
+                                 (double)op.out[0].cols;
+            t += std::max(4.0, bytes / 4.5e12 * 1e6);
+        }
+    }
+    return t;
+}
+
+// Called by the entry points for WS_AUTO / levels < 0 / WS_BASE_AUTO.
+int autotune_choice(ws_args &a, bool beta_nonzero) {
+    ws_args c = a;
+    const size_t budget = a.workspace ? (size_t)a.workspace_bytes : (size_t)-1;
+    const int rc = wsmul_autotune(a.m, a.k, a.n, a.p, a.dtype, budget, &c);
     (void)beta_nonzero;
+    if (rc != WS_OK)
+        return rc;
+    a.schedule = c.schedule;
+    a.levels = c.levels;
+    a.base = c.base;
     return WS_OK;
 }
 
 }  // namespace wsmul
+
+using namespace wsmul;
+
+extern "C" int wsmul_autotune(int64_t m, int64_t k, int64_t n, int64_t p, int dtype,
+                              size_t mem_budget, ws_args *choice) {
+    if (!choice || m < 0 || k < 0 || n < 0 || p < 2 || p >= (int64_t(1) << 24) ||
+        (dtype != WS_F64 && dtype != WS_I64)) {
+        set_error("wsmul_autotune: bad arguments");
+        return WS_EINVAL;
+    }
+    const bool beta_nz = ((choice->beta % p) + p) % p != 0;
+    Key key{m, k, n, p, dtype, beta_nz ? 1 : 0, choice->schedule, choice->levels, choice->base,
+            mem_budget};
+    if (key.schedule != WS_AUTO && key.schedule != WS_CLASSICAL && key.schedule != WS_TWO_TEMP &&
+        key.schedule != WS_OVERWRITE && key.schedule != WS_READONLY_INPLACE &&
+        key.schedule != WS_HL_THREE_TEMP && key.schedule != WS_OVR && key.schedule != WS_ACCR) {
+        set_error("wsmul_autotune: unknown schedule");
+        return WS_ESCHEDULE;
+    }
+    if (m == 0 || n == 0 || k == 0) {
+        choice->schedule = key.schedule == WS_AUTO ? WS_CLASSICAL : key.schedule;
+        choice->levels = 0;
+        choice->base = key.base == WS_BASE_AUTO ? WS_BASE_F64_MFMA : key.base;
+        return WS_OK;
+    }
+    Choice best{};
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        load_cache();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            best = it->second;
+            choice->schedule = best.schedule;
+            choice->levels = best.levels;
+            choice->base = best.base;
+            return WS_OK;
+        }
+    }
+    if (!search(key, best)) {
+        set_error("wsmul_autotune: no schedule fits the memory budget at this shape");
+        return WS_ENOMEM;
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[key] = best;
+        save_entry(key, best);
+    }
+    choice->schedule = best.schedule;
+    choice->levels = best.levels;
+    choice->base = best.base;
+    return WS_OK;
+}

@@ -57,6 +57,22 @@ namespace wsmul {
 
 void set_error(const std::string &msg) { g_err = msg; }
 
+void set_stats(const ws_stats &s) {
+    const uint64_t peak = std::max<uint64_t>(g_stats.peak_temp_bytes, s.workspace_bytes);
+    g_stats = s;
+    g_stats.peak_temp_bytes = peak;
+}
+
+hipStream_t default_stream() { return g_stream; }
+
+void set_batch_phases(uint64_t n) { g_stats.batch_phases = n; }
+
+void attached_workspace(void **ptr, size_t *bytes) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    *ptr = g_ws;
+    *bytes = g_ws_bytes;
+}
+
 std::shared_ptr<Plan> get_plan(const PlanKey &key) {
     std::lock_guard<std::mutex> lock(g_mu);
     auto it = g_plans.find(key);
@@ -95,7 +111,7 @@ int prepare(const ws_args *in, ws_args &a, PlanKey &key, Resolved &res) {
     if (a.base != WS_BASE_AUTO && a.base != WS_BASE_F64_MFMA && a.base != WS_BASE_I8_LIMBS)
         return fail(WS_EINVAL, "unknown base kind");
     const bool beta_nz = canon(a.beta, a.p) != 0;
-    if (a.schedule == WS_AUTO || a.levels < 0) {
+    if (a.schedule == WS_AUTO || a.levels < 0 || a.base == WS_BASE_AUTO) {
         const int rc = autotune_choice(a, beta_nz);
         if (rc != WS_OK)
             return rc;

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "device.hpp"
 #include "gemm_common.hpp"
@@ -159,15 +160,11 @@ hipError_t launch_add(const ws_op_desc &op, const DevBufs &bufs, int dtype, int6
 // supplies k = 4*(l/16) + s, so each lane's four A values are contiguous in
 // LDS; B uses the same k assignment.
 template <typename T, int BM, int BN, bool CENTRE, bool VEC2>
-__global__ __launch_bounds__(256, 2) void gemm_lds_kernel(GemmParams P) {
+__device__ __forceinline__ void gemm_lds_tile(const GemmParams &P, int32_t tm, int32_t tn,
+                                              double (*As)[BM * (16 + 2)], double (*Bs)[16 * BN]) {
     constexpr int BK = 16, APAD = 2;
     constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
     constexpr int AST = BK + APAD;                       // A row stride in LDS
-    __shared__ double As[2][BM * AST];
-    __shared__ double Bs[2][BK * BN];
-
-    int32_t tm, tn;
-    tile_of(P.tiles_m, P.tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
@@ -306,8 +303,7 @@ __global__ __launch_bounds__(256, 2) void gemm_lds_kernel(GemmParams P) {
     constexpr int LDS_DOUBLES = 2 * BM * AST + 2 * BK * BN;
     constexpr int ROUNDS = (BM * BN <= LDS_DOUBLES) ? 1 : 2;
     static_assert(BM * BN / ROUNDS <= LDS_DOUBLES, "epilogue staging does not fit");
-    double *stage = &As[0][0];
-    static_assert(sizeof(As) + sizeof(Bs) == LDS_DOUBLES * sizeof(double), "layout");
+    double *stage = &As[0][0];   // As and Bs are one contiguous block (see callers)
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -345,6 +341,22 @@ __global__ __launch_bounds__(256, 2) void gemm_lds_kernel(GemmParams P) {
 // from global memory, CH K-tiles of a wave at a time so that all of their
 // loads are in flight together; the epilogue's extra inputs are fetched at
 // kernel start; partial tiles are summed through LDS.
+// LDS operand buffers of one BM x BN tile, contiguous so that the epilogue
+// can reuse them as one staging area.
+template <int BM, int BN>
+struct LdsTile {
+    double As[2][BM * (16 + 2)];
+    double Bs[2][16 * BN];
+};
+
+template <typename T, int BM, int BN, bool CENTRE, bool VEC2>
+__global__ __launch_bounds__(256, 2) void gemm_lds_kernel(GemmParams P) {
+    __shared__ LdsTile<BM, BN> sh;
+    int32_t tm, tn;
+    tile_of(P.tiles_m, P.tiles_n, tm, tn);
+    gemm_lds_tile<T, BM, BN, CENTRE, VEC2>(P, tm, tn, sh.As, sh.Bs);
+}
+
 #ifndef WS_SK_WAVES
 #define WS_SK_WAVES 8   // waves splitting K in the small-product kernel
 #endif
@@ -612,6 +624,132 @@ hipError_t launch_range_check(const void *ptr, int64_t rows, int64_t cols, int64
         hipLaunchKernelGGL(range_check_kernel<double>, dim3(blocks), dim3(256), 0, stream,
                            static_cast<const double *>(ptr), rows, cols, ld, (double)p, flag);
     return hipGetLastError();
+}
+
+}  // namespace wsmul
+
+namespace wsmul {
+
+// ================================================================= batched
+// Persistent launch over many independent products.  The host groups the
+// operations of all products into phases -- phase j holds the j-th operation
+// of every product that has one -- so that the operations of a phase never
+// depend on each other; phases are ordered by the stream (one launch each,
+// all captured in one graph).  Each operation is cut into tasks: one 64 x 64
+// output tile of a base product or one chunk of an addition group.  The
+// workgroups of a launch walk the phase's task list round-robin (task w,
+// w + G, w + 2G, ... for workgroup w of G): no atomics and no waiting, every
+// workgroup ends after its last task.
+
+// Addition group of a batch op: elements [chunk*BATCH_CHUNK, ...) of the
+// M x N views, inputs ein[0..nin), outputs eout[0..nout).
+__device__ void batch_add_chunk(const GemmParams &P, int64_t chunk) {
+    const int64_t total = P.M * P.N;
+    const int64_t base = chunk * BATCH_CHUNK;
+#pragma unroll
+    for (int u = 0; u < BATCH_CHUNK / 256; ++u) {
+        const int64_t e = base + threadIdx.x + 256 * u;
+        if (e >= total)
+            break;
+        const int64_t r = e / P.N, c = e % P.N;
+        double x[WS_MAX_IN];
+#pragma unroll
+        for (int i = 0; i < WS_MAX_IN; ++i)
+            if (i < P.nin)
+                x[i] = static_cast<const double *>(P.ein[i])[r * P.eldi[i] + c];
+#pragma unroll
+        for (int o = 0; o < WS_MAX_OUT; ++o) {
+            if (o >= P.nout)
+                break;
+            double s = 0.0;
+#pragma unroll
+            for (int i = 0; i < WS_MAX_IN; ++i)
+                if (i < P.nin)
+                    s = fma(P.coef[o][i], x[i], s);
+            static_cast<double *>(P.eout[o])[r * P.eldo[o] + c] = mod_reduce(s, P.p, P.pinv);
+        }
+    }
+}
+
+// Base products run as 64 x 64 tiles here: with many products in flight the
+// launch is throughput-bound, and the smaller tile keeps register use low
+// enough for several workgroups per CU.
+__global__ __launch_bounds__(256) void batch_kernel(const BatchOp *ops, const int2 *tasks,
+                                                    int64_t ntasks) {
+    __shared__ LdsTile<64, 64> sh;
+    for (int64_t q = blockIdx.x; q < ntasks; q += gridDim.x) {
+        const int2 t = tasks[q];
+        const BatchOp &op = ops[t.x];
+        if (op.kind == WS_OP_GEMM) {
+            const int32_t tm = t.y / op.g.tiles_n, tn = t.y % op.g.tiles_n;
+            if (op.centre) {
+                if (op.vec2) gemm_lds_tile<double, 64, 64, true, true>(op.g, tm, tn, sh.As, sh.Bs);
+                else gemm_lds_tile<double, 64, 64, true, false>(op.g, tm, tn, sh.As, sh.Bs);
+            } else {
+                if (op.vec2) gemm_lds_tile<double, 64, 64, false, true>(op.g, tm, tn, sh.As, sh.Bs);
+                else gemm_lds_tile<double, 64, 64, false, false>(op.g, tm, tn, sh.As, sh.Bs);
+            }
+        } else {
+            batch_add_chunk(op.g, t.y);
+        }
+        __syncthreads();   // LDS is reused by the next task
+    }
+}
+
+hipError_t launch_batch(const BatchOp *ops, const int2 *tasks, int64_t ntasks, int grid,
+                        hipStream_t stream) {
+    if (ntasks == 0)
+        return hipSuccess;
+    const int g = (int)std::min<int64_t>(grid, ntasks);
+    hipLaunchKernelGGL(batch_kernel, dim3(g), dim3(256), 0, stream, ops, tasks, ntasks);
+    return hipGetLastError();
+}
+
+// Host helper: fill the GemmParams of one batch op from a plan operation.
+void fill_batch_op(BatchOp &b, const ws_op_desc &op, const DevBufs &bufs, int64_t p) {
+    std::memset(&b, 0, sizeof(b));
+    GemmParams &P = b.g;
+    const size_t esz = 8;
+    P.p = (double)p;
+    P.pinv = 1.0 / (double)p;
+    P.half = std::floor((double)p / 2.0);
+    P.nin = op.nin;
+    P.nout = op.nout;
+    b.kind = op.kind;
+    const int first = op.kind == WS_OP_GEMM ? 1 : 0;
+    for (int i = first; i < op.nin; ++i) {
+        P.ein[i] = static_cast<const char *>(bufs.ptr[op.in[i].buf]) + op.in[i].off * esz;
+        P.eldi[i] = op.in[i].ld;
+    }
+    for (int o = 0; o < op.nout; ++o) {
+        P.eout[o] = static_cast<char *>(bufs.ptr[op.out[o].buf]) + op.out[o].off * esz;
+        P.eldo[o] = op.out[o].ld;
+        for (int i = 0; i < op.nin; ++i)
+            P.coef[o][i] = (double)op.coef[o][i];
+    }
+    if (op.kind == WS_OP_GEMM) {
+        P.A = static_cast<const char *>(bufs.ptr[op.a.buf]) + op.a.off * esz;
+        P.B = static_cast<const char *>(bufs.ptr[op.b.buf]) + op.b.off * esz;
+        P.lda = op.a.ld;
+        P.ldb = op.b.ld;
+        P.M = op.a.rows;
+        P.K = op.a.cols;
+        P.N = op.b.cols;
+        P.alpha = (double)op.alpha;
+        const bool centre = fold_tiles(p, false, P.K) != 0;
+        P.kc_tiles = fold_tiles(p, centre, P.K);
+        b.centre = centre;
+        b.vec2 = (P.K % 2 == 0) && (P.N % 2 == 0) && (P.lda % 2 == 0) && (P.ldb % 2 == 0) &&
+                 aligned16(P.A) && aligned16(P.B);
+        b.tile = 64;
+        P.tiles_m = (int32_t)((P.M + b.tile - 1) / b.tile);
+        P.tiles_n = (int32_t)((P.N + b.tile - 1) / b.tile);
+        b.ntiles = P.tiles_m * P.tiles_n;
+    } else {
+        P.M = op.out[0].rows;
+        P.N = op.out[0].cols;
+        b.ntiles = (int32_t)((P.M * P.N + BATCH_CHUNK - 1) / BATCH_CHUNK);
+    }
 }
 
 }  // namespace wsmul

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "gemm_common.hpp"
 #include "wsmul.h"
 
 namespace wsmul {
@@ -26,5 +27,23 @@ hipError_t launch_gemm(const ws_op_desc &op, const DevBufs &bufs, int dtype, int
 // [0, p).  The flag must be cleared by the caller beforehand.
 hipError_t launch_range_check(const void *ptr, int64_t rows, int64_t cols, int64_t ld,
                               int dtype, int64_t p, int *flag, hipStream_t stream);
+
+// One operation of a product in a batched launch (see launch_batch).
+constexpr int BATCH_CHUNK = 256 * 8;   // elements per addition task
+struct BatchOp {
+    GemmParams g;    // base product, or addition group (inputs ein[0..nin), M x N views)
+    int32_t kind;    // WS_OP_ADD or WS_OP_GEMM
+    int32_t tile;    // base product: 64
+    int32_t centre, vec2;
+    int32_t ntiles;  // tasks of this operation
+    int32_t phase;   // position of the operation in its product's plan
+};
+
+void fill_batch_op(BatchOp &b, const ws_op_desc &op, const DevBufs &bufs, int64_t p);
+
+// One persistent launch over the independent tasks of one phase: workgroup w
+// of `grid` runs tasks w, w + grid, ...
+hipError_t launch_batch(const BatchOp *ops, const int2 *tasks, int64_t ntasks, int grid,
+                        hipStream_t stream);
 
 }  // namespace wsmul

@@ -13,6 +13,12 @@
 namespace wsmul {
 
 void set_error(const std::string &msg);
+void set_stats(const ws_stats &s);
+void set_batch_phases(uint64_t n);
+hipStream_t default_stream();
+void attached_workspace(void **ptr, size_t *bytes);
+// Estimated time (microseconds) of a plan under a base kind.
+double plan_cost_us(const Plan &plan, int base);
 std::shared_ptr<Plan> get_plan(const PlanKey &key);
 int prepare(const ws_args *in, ws_args &a, PlanKey &key, Resolved &res);
 int execute(const ws_args &a, const PlanKey &key);

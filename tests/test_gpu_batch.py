@@ -1,0 +1,132 @@
+"""GPU parity of the batched persistent launch and its hipGraph replay.
+
+Each product of a batch is checked against the oracle: small batches in full,
+the 2000-product workload (sizes log-uniform in [64, 2048], three moduli) on
+sampled entries computed one by one, in the launch configuration the
+benchmark times (one graph replay)."""
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_0707_2347_amd import capi, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _mk_batch(specs, seed):
+    """specs: (m, k, n, p, schedule, levels, beta).  Returns host and device data."""
+    t = _torch()
+    host, dev, args = [], [], []
+    rng = np.random.default_rng(seed)
+    for i, (m, k, n, p, sched, lev, beta) in enumerate(specs):
+        A, B, C = inputs.uniform(seed * 1000 + i, m, k, n, p, with_c=True)
+        dA = t.from_numpy(A.astype(np.float64)).cuda()
+        dB = t.from_numpy(B.astype(np.float64)).cuda()
+        dC = t.from_numpy(C.astype(np.float64)).cuda()
+        alpha = int(rng.integers(1, p))
+        host.append((A, B, C, alpha, beta, p))
+        dev.append((dA, dB, dC))
+        args.append(capi.make_args(m, k, n, p, dA, dB, dC, alpha, beta, sched, lev,
+                                   base=capi.WS_BASE_F64_MFMA,
+                                   stream=t.cuda.current_stream()))
+    return host, dev, args
+
+
+SPECS = [
+    (64, 64, 64, 65521, capi.WS_CLASSICAL, 0, 0), (100, 37, 213, 8388593, capi.WS_CLASSICAL, 0, 5),
+    (128, 128, 128, 1048573, capi.WS_TWO_TEMP, 1, 0), (256, 256, 256, 65521, capi.WS_TWO_TEMP, 2, 3),
+    (200, 300, 150, 8388593, capi.WS_TWO_TEMP, 2, 0), (256, 256, 256, 65521, capi.WS_OVERWRITE, 2, 0),
+    (256, 128, 256, 8388593, capi.WS_READONLY_INPLACE, 2, 0), (96, 96, 96, 65521, capi.WS_HL_THREE_TEMP, 1, 7),
+    (333, 444, 555, 1048573, capi.WS_AUTO, -1, 0), (1024, 512, 768, 8388593, capi.WS_AUTO, -1, 9),
+    (1, 1, 1, 65521, capi.WS_CLASSICAL, 0, 1), (65, 2047, 17, 8388593, capi.WS_CLASSICAL, 0, 0),
+]
+
+
+def test_batched_mixed():
+    t = _torch()
+    host, dev, args = _mk_batch(SPECS, 3)
+    st = capi.wsmul_batched(args, capi.WS_FLAG_SYNC)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    t.cuda.synchronize()
+    for (A, B, C, alpha, beta, p), (dA, dB, dC) in zip(host, dev):
+        got = dC.cpu().numpy().astype(np.int64)
+        assert np.array_equal(got, ref.matmul_mod_p(A, B, C, alpha, beta, p))
+
+
+def test_graph_replays_with_eager_work_between():
+    t = _torch()
+    specs = [s for s in SPECS if s[4] != capi.WS_OVERWRITE]
+    host, dev, args = _mk_batch(specs, 4)
+    st, handle = capi.wsmul_graph_capture(args)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    try:
+        for rep in range(3):
+            # eager work between replays: fresh inputs and C, plus unrelated kernels
+            newhost = []
+            for i, ((A, B, C, alpha, beta, p), (dA, dB, dC)) in enumerate(zip(host, dev)):
+                A2, B2, C2 = inputs.uniform(500 + 10 * rep + i, A.shape[0], A.shape[1], B.shape[1],
+                                            p, with_c=True)
+                dA.copy_(t.from_numpy(A2.astype(np.float64)))
+                dB.copy_(t.from_numpy(B2.astype(np.float64)))
+                dC.copy_(t.from_numpy(C2.astype(np.float64)))
+                newhost.append((A2, B2, C2, alpha, beta, p))
+            scratch = t.ones(1 << 20, device="cuda:0").sum()
+            t.cuda.synchronize()
+            assert capi.wsmul_graph_launch(handle, t.cuda.current_stream()) == capi.WS_OK
+            assert capi.wsmul_graph_check(handle, t.cuda.current_stream()) == capi.WS_OK
+            t.cuda.synchronize()
+            assert float(scratch) == float(1 << 20)
+            for (A, B, C, alpha, beta, p), (dA, dB, dC) in zip(newhost, dev):
+                got = dC.cpu().numpy().astype(np.int64)
+                assert np.array_equal(got, ref.matmul_mod_p(A, B, C, alpha, beta, p)), rep
+    finally:
+        capi.wsmul_graph_destroy(handle)
+
+
+def test_batch_workload_2000_sampled():
+    """All 2000 products of the batch workload in one graph replay; 6 sampled
+    entries per product, each computed by the oracle when its inputs are made."""
+    t = _torch()
+    probs = inputs.batch_problems()
+    assert len(probs) == 2000
+    rng = np.random.default_rng(11)
+    args, dev, want = [], [], []
+    for pr in probs:
+        A, B = inputs.batch_inputs(pr)
+        m, k, n, p = pr["m"], pr["k"], pr["n"], pr["p"]
+        rows = rng.integers(0, m, size=6)
+        cols = rng.integers(0, n, size=6)
+        want.append((rows, cols, ref.matmul_entries(A, B, None, 1, 0, p, rows, cols)))
+        dA = t.from_numpy(A).cuda()
+        dB = t.from_numpy(B).cuda()
+        dC = t.full((m, n), -1.0, dtype=t.float64, device="cuda:0")
+        dev.append((dA, dB, dC))
+        args.append(capi.make_args(m, k, n, p, dA, dB, dC, 1, 0, capi.WS_AUTO, -1,
+                                   base=capi.WS_BASE_F64_MFMA, stream=t.cuda.current_stream()))
+    st, handle = capi.wsmul_graph_capture(args)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    try:
+        assert capi.wsmul_graph_launch(handle, t.cuda.current_stream()) == capi.WS_OK
+        assert capi.wsmul_graph_check(handle, t.cuda.current_stream()) == capi.WS_OK
+        t.cuda.synchronize()
+        for (rows, cols, w), (dA, dB, dC) in zip(want, dev):
+            got = dC[t.from_numpy(rows).cuda(), t.from_numpy(cols).cuda()].cpu().numpy()
+            assert np.array_equal(got.astype(np.int64), w)
+    finally:
+        capi.wsmul_graph_destroy(handle)
+
+
+@pytest.mark.parametrize("shape,p,beta", [((300, 200, 100), 65521, 0), ((1024, 1024, 1024), 1048573, 0),
+                                          ((512, 512, 512), 8388593, 3)])
+def test_autotuned_calls(shape, p, beta):
+    from .gpu_util import call
+    m, k, n = shape
+    A, B, C = inputs.uniform(21, m, k, n, p, with_c=True)
+    st, C2, _, _ = call(capi.WS_AUTO, A, B, C, 5, beta, p, -1, base=capi.WS_BASE_AUTO)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, 5, beta, p))
