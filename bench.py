@@ -31,6 +31,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def kernels_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "gemm_common.hpp", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_0707_2347_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(gemm_dominant):
+    """HBM bytes per launch of the dominant kernel, from the FETCH_SIZE and
+    WRITE_SIZE counter runs recorded in profiles/ (scaled by the plain-copy
+    calibration there); None when the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_acc_4096_p65521_l3.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernels_digest") != kernels_digest():
+        return None
+    key = "base_product" if gemm_dominant else "addition_group"
+    return rec.get(key, {}).get("bytes_per_launch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -39,8 +62,8 @@ def main():
     ap.add_argument("--levels", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparator schedules")
-    ap.add_argument("--traffic", default=None,
-                    help="JSON file with per-launch HBM bytes of the dominant kernel")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run plain device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -51,6 +74,16 @@ def main():
     import torch
 
     from paper_0707_2347_amd import capi, inputs
+
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8, "copies": 5}))
+        return
 
     w = inputs.WORKLOADS["acc_4096_p65521_l3"]
     m, k, n, p = w["m"], w["k"], w["n"], w["p"]
@@ -96,7 +129,8 @@ def main():
     # kernel-class times from events on the launch stream (separate traced steps)
     capi.wsmul_reset_stats()
     traced = mkargs(capi.WS_TWO_TEMP, ws, nbytes, flags=capi.WS_FLAG_TRACE)
-    for _ in range(max(1, min(args.steps, 5))):
+    ntraced = max(1, min(args.steps, 5))
+    for _ in range(ntraced):
         capi.check(capi.wsmul_mod_p_ex(traced))
     tr = capi.wsmul_get_trace()
     gemm_avg_ms = tr.gemm_ms / max(tr.gemm_launches, 1)
@@ -107,9 +141,7 @@ def main():
     add_gbs = add_bytes_per / (add_avg_ms * 1e-3) / 1e9
     log("trace: base products %d x %.4f ms (%.2f TFLOP/s), additions %d x %.4f ms (%.0f GB/s)"
         % (tr.gemm_launches, gemm_avg_ms, gemm_tfs, tr.add_launches, add_avg_ms, add_gbs))
-    traffic = None
-    if args.traffic and os.path.exists(args.traffic):
-        traffic = json.load(open(args.traffic)).get("bytes_per_launch")
+    traffic = measured_traffic(tr.gemm_ms >= tr.add_ms)
     if tr.gemm_ms >= tr.add_ms:
         roofline = {"bound": "mfma", "kernel": "base product (f64 16x16x4 matrix cores)",
                     "achieved": round(gemm_tfs, 3), "peak": PEAK_F64_MFMA_TFLOPS,
@@ -126,8 +158,8 @@ def main():
     extra = {"peak_temp_bytes": int(stats.workspace_bytes),
              "launches_per_step": {"base_products": int(stats.gemm_launches),
                                    "addition_groups": int(stats.add_launches)},
-             "kernel_time_per_step_ms": {"base_products": round(tr.gemm_ms / 5, 4),
-                                         "additions": round(tr.add_ms / 5, 4)}}
+             "kernel_time_per_step_ms": {"base_products": round(tr.gemm_ms / ntraced, 4),
+                                         "additions": round(tr.add_ms / ntraced, 4)}}
 
     # ---------------------------------------------------- comparators
     if not args.no_compare:
@@ -182,14 +214,17 @@ def main():
         ref.matmul_mod_p(Ai[:rows], Bi, Ci[:rows], 1, 1, p, threads=threads)
         dt = time.perf_counter() - t_s
         rows = int(min(m, max(16, rows * 12.0 / max(dt, 1e-3))))
-        log("cpu baseline: oracle on %d rows x %d x %d, %d threads" % (rows, k, n, threads))
+        reps = 1 if rows < m else max(1, int(10.0 / max(dt * m / 16.0, 1e-3)))
+        log("cpu baseline: oracle on %d rows x %d x %d, %d threads, %d run(s)"
+            % (rows, k, n, threads, reps))
         t_s = time.perf_counter()
-        ref.matmul_mod_p(Ai[:rows], Bi, Ci[:rows], 1, 1, p, threads=threads)
-        dt = time.perf_counter() - t_s
+        for _ in range(reps):
+            ref.matmul_mod_p(Ai[:rows], Bi, Ci[:rows], 1, 1, p, threads=threads)
+        dt = (time.perf_counter() - t_s) / reps
         cpu = {"value": round(2.0 * rows * k * n / dt / 1e9, 3), "unit": "Gop/s",
                "cores": threads, "kind": "oracle",
-               "sample": "rows 0..%d of the same product (%d x %d x %d), %.1f s"
-                         % (rows - 1, rows, k, n, dt)}
+               "sample": "rows 0..%d of the same product (%d x %d x %d), %d run(s) of %.1f s"
+                         % (rows - 1, rows, k, n, reps, dt)}
 
     out = {"metric": "mod-p matmul effective Gop/s (2mnk/s) + peak temp bytes vs classical "
                      "mod-p GEMM",
