@@ -6,8 +6,9 @@
 //   base products, binary64 matrix cores: 58 TFLOP/s for the 128 x 128 tile
 //     class (x0.87 when the accumulators must be folded), 30 TFLOP/s for the
 //     64 x 64 class, 19 TFLOP/s for the split-K class, 8 us floor per launch;
-//   base products, 8-bit digits: 96 / 83 / 65 / 30 TFLOP/s (equivalent) by
-//     tile count, plus the digit split passes (bytes at 5 TB/s);
+//   base products, 8-bit digits: 215 / 190 / 140 / 100 / 40 TFLOP/s
+//     (equivalent) by 128 x 128 tile count, plus the digit split passes
+//     (bytes at 5 TB/s);
 //   addition groups: bytes moved at 4.5 TB/s, 4 us floor per launch.
 // The cheapest candidate whose temporaries fit the memory budget wins.
 // Overwriting schedules are never chosen automatically (they destroy A, B).
@@ -39,7 +40,11 @@ double gemm_f64_us(int64_t M, int64_t N, int64_t K, int64_t p) {
 double gemm_digits_us(int64_t M, int64_t N, int64_t K) {
     const double flops = 2.0 * (double)M * (double)N * (double)K;
     const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
-    const double rate = tiles >= 1024 ? 96e12 : (tiles >= 256 ? 83e12 : (tiles >= 64 ? 65e12 : 30e12));
+    const double rate = tiles >= 8192   ? 215e12
+                        : tiles >= 2048 ? 190e12
+                        : tiles >= 512  ? 140e12
+                        : tiles >= 128  ? 100e12
+                                        : 40e12;
     const double split_bytes = 11.0 * ((double)M * (double)K + (double)K * (double)N);
     return std::max(8.0, flops / rate * 1e6) + 2.0 * 5.0 + split_bytes / 5e12 * 1e6;
 }

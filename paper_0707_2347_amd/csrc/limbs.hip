@@ -24,7 +24,6 @@ namespace {
 
 constexpr int TILE = 128;     // output tile per workgroup (both dimensions)
 constexpr int KSTEP = 64;     // inner dimension per matrix-core op
-constexpr int ROWB = 80;      // LDS bytes per digit row (64 + 16: no bank conflicts)
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
@@ -114,11 +113,17 @@ struct DigitParams {
 
 // 128 x 128 output tile, four waves in a 2 x 2 grid (64 x 64 each, one wave
 // per SIMD so that the five int32 accumulator sets -- one per weight class,
-// 320 registers -- fit without spilling), digit tiles of 64 inner elements
-// double-buffered through LDS.
+// 320 registers -- fit), digit tiles of 64 inner elements double-buffered in
+// LDS and filled by direct global-to-LDS loads issued one K-step ahead (no
+// staging registers).  A load instruction places lane l's 16 bytes at
+// base + 16*l, so each instruction fills 16 rows of 64 bytes; within a row
+// the four 16-byte chunks are stored XOR-swizzled (chunk c of row r at slot
+// c ^ ((r >> 2) & 3)) so that the 16 lanes reading one chunk of 16
+// consecutive rows hit 16 distinct slots of the 256 LDS bytes they span.
 template <typename T>
 __global__ __launch_bounds__(256) void gemm_digits_kernel(DigitParams D) {
-    __shared__ __attribute__((aligned(16))) int8_t lds[2][2][3][TILE * ROWB];   // [stage][A|B][digit][row*ROWB]
+    constexpr int PLANE = TILE * KSTEP;                     // bytes of one digit tile
+    __shared__ __attribute__((aligned(16))) int8_t lds[2][2][3][PLANE];   // [stage][A|B][digit]
     const GemmParams &P = D.g;
     int32_t tm, tn;
     tile_of(P.tiles_m, P.tiles_n, tm, tn);
@@ -128,30 +133,23 @@ __global__ __launch_bounds__(256) void gemm_digits_kernel(DigitParams D) {
     const int li = lane & 15, g = lane >> 4;
     const int64_t plA = D.Mp * D.Kp, plB = D.Np * D.Kp;
 
-    // Staging: A and B each 3 digits x 128 rows x 64 bytes = 1536 chunks of
-    // 16 bytes, i.e. six of each per thread, moved in three groups (two of A
-    // and two of B each) interleaved with the three digit rounds of the
-    // matrix-core loop, so that only one group occupies registers at a time.
-    constexpr int CPT = 3 * TILE * KSTEP / 16 / 256;
-    static_assert(CPT == 6, "three groups of two chunks");
-    uint4 sa[2], sb[2];
-    auto gload = [&](int grp, int64_t k0) {
+    // 48 load instructions per K-step (2 operands x 3 digits x 8 blocks of
+    // 16 rows), twelve per wave.
+    auto issue = [&](int st, int64_t k0) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int q = tid + 256 * (2 * grp + j);
-            const int d = q / (TILE * 4), row = (q % (TILE * 4)) / 4, part = q % 4;
-            sa[j] = *reinterpret_cast<const uint4 *>(D.Ad + d * plA + (m0 + row) * D.Kp + k0 + 16 * part);
-            sb[j] = *reinterpret_cast<const uint4 *>(D.Bd + d * plB + (n0 + row) * D.Kp + k0 + 16 * part);
+        for (int j = 0; j < 12; ++j) {
+            const int i = wave + 4 * j;
+            const int op = i / 24, d = (i % 24) / 8, blk = i % 8;
+            const int row = blk * 16 + (lane >> 2), slot = lane & 3;
+            const int chunk = slot ^ ((row >> 2) & 3);
+            const int8_t *src = op == 0 ? D.Ad + d * plA + (m0 + row) * D.Kp
+                                        : D.Bd + d * plB + (n0 + row) * D.Kp;
+            __builtin_amdgcn_global_load_lds(src + k0 + 16 * chunk, &lds[st][op][d][blk * 1024], 16, 0, 0);
         }
     };
-    auto sstore = [&](int grp, int st) {
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int q = tid + 256 * (2 * grp + j);
-            const int d = q / (TILE * 4), row = (q % (TILE * 4)) / 4, part = q % 4;
-            *reinterpret_cast<uint4 *>(&lds[st][0][d][row * ROWB + 16 * part]) = sa[j];
-            *reinterpret_cast<uint4 *>(&lds[st][1][d][row * ROWB + 16 * part]) = sb[j];
-        }
+    auto frag = [&](int st, int op, int d, int row) {
+        return *reinterpret_cast<const i32x4 *>(
+            &lds[st][op][d][row * KSTEP + 16 * (g ^ ((row >> 2) & 3))]);
     };
 
     i32x4 acc[5][4][4];
@@ -164,35 +162,26 @@ __global__ __launch_bounds__(256) void gemm_digits_kernel(DigitParams D) {
                 acc[w][i][j] = i32x4{0, 0, 0, 0};
 
     const int64_t ksteps = D.Kp / KSTEP;
-    if (ksteps > 0) {
-#pragma unroll
-        for (int grp = 0; grp < 3; ++grp) {
-            gload(grp, 0);
-            sstore(grp, 0);
-        }
-    }
+    if (ksteps > 0)
+        issue(0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     for (int64_t t = 0; t < ksteps; ++t) {
         const int cur = (int)(t & 1);
-        const bool more = t + 1 < ksteps;
-        // B fragments of digit b stay in registers while the A fragments of
-        // each digit a are read from LDS for the (a, b) pair.
+        if (t + 1 < ksteps)
+            issue(cur ^ 1, (t + 1) * KSTEP);
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            if (more)
-                gload(b, (t + 1) * KSTEP);
             i32x4 bf[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                bf[j] = *reinterpret_cast<const i32x4 *>(
-                    &lds[cur][1][b][(wn * 64 + j * 16 + li) * ROWB + 16 * g]);
+                bf[j] = frag(cur, 1, b, wn * 64 + j * 16 + li);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 i32x4 af[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    af[i] = *reinterpret_cast<const i32x4 *>(
-                        &lds[cur][0][a][(wm * 64 + i * 16 + li) * ROWB + 16 * g]);
+                    af[i] = frag(cur, 0, a, wm * 64 + i * 16 + li);
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -200,9 +189,8 @@ __global__ __launch_bounds__(256) void gemm_digits_kernel(DigitParams D) {
                         acc[a + b][i][j] =
                             __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[j], acc[a + b][i][j], 0, 0, 0);
             }
-            if (more)
-                sstore(b, cur ^ 1);
         }
+        __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of the next K-step have landed
         __syncthreads();
     }
 
