@@ -491,6 +491,217 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_sk_kernel(GemmParams P) {
     }
 }
 
+// Base products whose shape is whole 32 x 32 output tiles and 64-deep
+// inner chunks with 16-byte aligned rows (every Winograd leaf of a
+// power-of-two product): one 32 x 32 output tile per workgroup over the full
+// inner dimension, split among the waves.  Wave w owns the SK-deep
+// sub-chunks w, w + WAVES, w + 2*WAVES, ... of the inner dimension; it
+// streams their A (32 x SK) and B (SK x 32) blocks into STAGES private LDS
+// buffers by direct global-to-LDS loads, waits on its own load counter and
+// needs no workgroup barrier until the partial tiles are summed in LDS
+// before the fused epilogue.
+//
+// A load instruction writes lane l's 16 bytes at base + 16*l, so the LDS
+// layout is fixed by the instruction and the permutation lives in the global
+// addresses: 16-byte pieces are XOR-swizzled within each A-row and B-row so
+// that the matrix-core operand reads spread over the LDS banks.
+#ifndef WS_DMA_WAVES
+#define WS_DMA_WAVES 8
+#endif
+#ifndef WS_DMA_STAGES
+#define WS_DMA_STAGES 2
+#endif
+#ifndef WS_DMA_SK
+#define WS_DMA_SK 16
+#endif
+namespace dmak {
+constexpr int TM = 32;
+// Piece swizzles: A-rows of SK*8 bytes, B-rows of 256 bytes.
+template <int SK>
+__device__ __forceinline__ int aswz(int r) {
+    return SK == 16 ? ((r & 7) ^ ((r >> 3) & 1)) : (((r >> 2) & 3) ^ (((r >> 1) & 1) << 1));
+}
+template <int SK>
+__device__ __forceinline__ int bswz(int k) {
+    return SK == 16 ? 8 * ((k >> 2) & 1) : 8 * ((k >> 1) & 1);
+}
+// Wait until at most n of this wave's loads are in flight (n a multiple of 4).
+__device__ __forceinline__ void wait_loads(int n) {
+    if (n >= 24) asm volatile("s_waitcnt vmcnt(24)" ::: "memory");
+    else if (n >= 16) asm volatile("s_waitcnt vmcnt(16)" ::: "memory");
+    else if (n >= 12) asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
+    else if (n >= 8) asm volatile("s_waitcnt vmcnt(8)" ::: "memory");
+    else if (n >= 4) asm volatile("s_waitcnt vmcnt(4)" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+}  // namespace dmak
+
+template <typename T>
+struct alignas(16) Pair {
+    T x, y;
+};
+
+template <typename T, bool CENTRE, int WAVES, int STAGES, int SK>
+__global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
+    using namespace dmak;
+    constexpr int NT = 64 * WAVES;
+    constexpr int EPT = TM * TM / NT;
+    constexpr int S = SK / 4;                        // matrix-core steps per sub-chunk
+    constexpr int A_BYTES = TM * SK * 8, SUB_BYTES = 2 * A_BYTES;
+    constexpr int AROWS = 1024 / (SK * 8);           // A-rows per load instruction
+    constexpr int AI = TM / AROWS, BI = SK / 4;      // load instructions for A, for B
+    constexpr int LPS = AI + BI;                     // per sub-chunk
+    // Rows of the partial tiles padded by two when the buffers have room.
+    constexpr int PROW = WAVES * TM * (TM + 2) * 8 <= WAVES * STAGES * SUB_BYTES ? TM + 2 : TM;
+    constexpr int PSTRIDE = TM * PROW;
+    static_assert(SK == 8 || SK == 16, "sub-chunks of 8 or 16");
+    static_assert(STAGES >= 2 && (STAGES - 2) * LPS <= 24, "load counter range");
+    static_assert(WAVES * PSTRIDE * 8 <= WAVES * STAGES * SUB_BYTES, "partials fit the buffers");
+    __shared__ __attribute__((aligned(16))) char lds[WAVES * STAGES * SUB_BYTES];
+    int32_t tm, tn;
+    tile_of(P.tiles_m, P.tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TM;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, kq = lane >> 4;
+    const char *A = static_cast<const char *>(P.A);
+    const char *B = static_cast<const char *>(P.B);
+    char *mine = lds + wave * (STAGES * SUB_BYTES);
+
+    // Epilogue inputs do not depend on the product: fetch them first.
+    double ex[EPT][WS_MAX_IN];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = tid + NT * u;
+        epilogue_load<T>(P, ex[u], m0 + e / TM, n0 + e % TM);
+    }
+
+    const int64_t nsub = (P.K / SK - wave + WAVES - 1) / WAVES;   // this wave's sub-chunks
+    // Sub-chunk u of this wave into buffer st.
+    auto issue = [&](int st, int64_t u) {
+        const int64_t k0 = (wave + (int64_t)WAVES * u) * SK;
+        char *base = mine + st * SUB_BYTES;
+#pragma unroll
+        for (int j = 0; j < AI; ++j) {
+            const int r = AROWS * j + lane / (SK / 2);
+            const int piece = (lane % (SK / 2)) ^ aswz<SK>(r);
+            __builtin_amdgcn_global_load_lds(A + ((m0 + r) * P.lda + k0) * 8 + piece * 16,
+                                             base + j * 1024, 16, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < BI; ++j) {
+            const int k = 4 * j + (lane >> 4), piece = (lane & 15) ^ bswz<SK>(k);
+            __builtin_amdgcn_global_load_lds(B + ((k0 + k) * P.ldb + n0) * 8 + piece * 16,
+                                             base + A_BYTES + j * 1024, 16, 0, 0);
+        }
+    };
+    auto cvt = [&](T raw) {
+        const double x = to_f64(raw);
+        return (CENTRE && x > P.half) ? x - P.p : x;
+    };
+
+    f64x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    int since_fold = 0;
+
+#pragma unroll
+    for (int st = 0; st < STAGES - 1; ++st)
+        if (st < nsub)
+            issue(st, st);
+    // Step u: sub-chunk u resident (only sub-chunks issued after it may be in
+    // flight), refill the buffer of sub-chunk u-1, read the fragments of u
+    // (lane (li, kq) holds inner indices S*kq + s, s < S) and multiply.
+    for (int64_t u = 0; u < nsub; ++u) {
+        wait_loads(LPS * (int)std::max<int64_t>(0, std::min<int64_t>(u + STAGES - 2, nsub - 1) - u));
+        if (u + STAGES - 1 < nsub)
+            issue((int)((u + STAGES - 1) % STAGES), u + STAGES - 1);
+        const char *sa = mine + (int)(u % STAGES) * SUB_BYTES;
+        const char *sb = sa + A_BYTES;
+        double a[2][S], b[2][S];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int r = 16 * i + li;
+#pragma unroll
+            for (int h = 0; h < S / 2; ++h) {
+                const Pair<T> v = *reinterpret_cast<const Pair<T> *>(
+                    sa + r * (SK * 8) + (((S / 2) * kq + h) ^ aswz<SK>(r)) * 16);
+                a[i][2 * h] = cvt(v.x);
+                a[i][2 * h + 1] = cvt(v.y);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int k = S * kq + s, col = 16 * j + li;
+                b[j][s] = cvt(*reinterpret_cast<const T *>(
+                    sb + k * (TM * 8) + ((col >> 1) ^ bswz<SK>(k)) * 16 + (col & 1) * 8));
+            }
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+        if (P.kc_tiles > 0 && ++since_fold == P.kc_tiles) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[i][j][v] = mod_reduce(acc[i][j][v], P.p, P.pinv);
+            since_fold = 0;
+        }
+    }
+
+    // Partial tiles through LDS, summed by every thread for its epilogue
+    // elements.  When the whole inner dimension fits below 2^53 the raw
+    // partials are summed and reduced once.  Output of the 16 x 16 x 4 op:
+    // lane l, element v is row l/16 + 4v, column l%16.
+    const double mx = CENTRE ? P.half + 1.0 : P.p - 1.0;
+    const bool raw = P.kc_tiles == 0 && (double)P.K * mx * mx < 9.0e15;
+    __syncthreads();
+    double *part = reinterpret_cast<double *>(lds);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                part[wave * PSTRIDE + (16 * i + kq + 4 * v) * PROW + 16 * j + li] =
+                    raw ? acc[i][j][v] : mod_reduce(acc[i][j][v], P.p, P.pinv);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const int e = tid + NT * u;
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w)
+            sum += part[w * PSTRIDE + (e / TM) * PROW + e % TM];
+        ex[u][0] = product_residue(P, sum);
+        epilogue_store<T>(P, ex[u], m0 + e / TM, n0 + e % TM);
+    }
+}
+
+// Fold period of gemm_dma_kernel in sub-chunks: each adds sk products of
+// magnitude at most m^2 to a wave's accumulators; 0 if a wave's whole share
+// of the inner dimension fits below 2^53.
+static int32_t fold_chunks(int64_t p, bool centre, int64_t K, int waves, int sk) {
+    const double mx = centre ? (double)((p - 1) / 2 + 1) : (double)(p - 1);
+    const double lim = 9007199254740992.0 - 4.0 * (double)p;
+    const double t = std::floor(lim / std::max((double)sk * mx * mx, 1.0));
+    const double per_wave = std::ceil((double)K / (double)sk / (double)waves);
+    if (t >= per_wave)
+        return 0;
+    return (int32_t)std::max(1.0, std::min(t, 1.0e9));
+}
+
+
 // Fold period: the largest number of K-tiles t with
 // t*16*m^2 + 2p < 2^53 where m bounds |operand| (p-1, or (p-1)/2 centred).
 static int32_t fold_tiles(int64_t p, bool centre, int64_t K) {
@@ -532,6 +743,16 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
             if (vec2) hipLaunchKernelGGL((gemm_lds_kernel<T, 64, 64, false, true>), grid, block, 0, s, P);
             else hipLaunchKernelGGL((gemm_lds_kernel<T, 64, 64, false, false>), grid, block, 0, s, P);
         }
+    } else if (P.M % 32 == 0 && P.N % 32 == 0 && P.K % 64 == 0 && P.K > 0 && P.lda % 2 == 0 &&
+               P.ldb % 2 == 0 && aligned16(P.A) && aligned16(P.B)) {
+        constexpr int W = WS_DMA_WAVES, ST = WS_DMA_STAGES, SK = WS_DMA_SK;
+        const bool c2 = fold_chunks((int64_t)P.p, false, P.K, W, SK) != 0;
+        P.kc_tiles = fold_chunks((int64_t)P.p, c2, P.K, W, SK);
+        P.tiles_m = (int32_t)(P.M / 32);
+        P.tiles_n = (int32_t)(P.N / 32);
+        const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(64 * W);
+        if (c2) hipLaunchKernelGGL((gemm_dma_kernel<T, true, W, ST, SK>), grid, block, 0, s, P);
+        else hipLaunchKernelGGL((gemm_dma_kernel<T, false, W, ST, SK>), grid, block, 0, s, P);
     } else {
         P.tiles_m = (int32_t)((P.M + 31) / 32);
         P.tiles_n = (int32_t)((P.N + 31) / 32);

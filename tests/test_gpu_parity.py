@@ -54,6 +54,35 @@ def test_extreme_entries_long_k():
     assert np.all(C2 == k % p)
 
 
+# Whole 32 x 32 tiles and 64-deep inner chunks with aligned rows: the
+# pipelined small-product kernel, both storage types, folds included.
+@pytest.mark.parametrize("dtype", [capi.WS_F64, capi.WS_I64])
+@pytest.mark.parametrize("shape,p", [((32, 64, 32), 65521), ((96, 640, 160), 8388593),
+                                     ((128, 128, 128), 1048573), ((256, 4096, 256), 8388593),
+                                     ((64, 2048, 64), 16777213), ((512, 512, 512), 65521),
+                                     ((32, 8192, 64), 16777213)])
+def test_whole_tile_products(shape, p, dtype):
+    m, k, n = shape
+    print("whole-tile", shape, p, dtype, flush=True)
+    A, B, C = inputs.uniform(m + 3 * k + 7 * n, m, k, n, p, with_c=True)
+    for alpha, beta in [(1, 0), (3, 1), (p - 1, p - 5)]:
+        st, C2, _, _ = call(capi.WS_CLASSICAL, A, B, C, alpha, beta, p, 0, dtype=dtype)
+        assert st == capi.WS_OK, capi.wsmul_last_error()
+        assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, alpha, beta, p)), (alpha, beta)
+
+
+def test_whole_tile_largest_centred_sums():
+    """Centred operands of the largest magnitude, (p-1)/2 against -(p-1)/2,
+    over 8192 inner indices: every partial sum needs the periodic folds."""
+    p = 16777213
+    m, k, n = 64, 8192, 96
+    A = np.full((m, k), (p - 1) // 2, dtype=np.int64)
+    B = np.full((k, n), (p + 1) // 2, dtype=np.int64)
+    st, C2, _, _ = call(capi.WS_CLASSICAL, A, B, None, 1, 0, p, 0)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, None, 1, 0, p))
+
+
 CASES = [
     (capi.WS_TWO_TEMP, (64, 64, 64), 1, False), (capi.WS_TWO_TEMP, (128, 128, 128), 3, False),
     (capi.WS_TWO_TEMP, (128, 64, 256), 2, False), (capi.WS_TWO_TEMP, (192, 128, 64), 2, False),
