@@ -70,7 +70,7 @@ int plan_batch(const ws_args *probs, int count, Batch &b) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    b.grid = std::max(1, cus * 2);
+    b.grid = std::max(1, cus * batch_blocks_per_cu());
     return WS_OK;
 }
 

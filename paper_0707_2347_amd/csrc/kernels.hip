@@ -898,9 +898,16 @@ __device__ void batch_add_chunk(const GemmParams &P, int64_t chunk) {
 __global__ __launch_bounds__(256) void batch_kernel(const BatchOp *ops, const int2 *tasks,
                                                     int64_t ntasks) {
     __shared__ LdsTile<64, 64> sh;
+    // Records and tasks do not change during the launch: read them through
+    // the constant address space, so that the parameters are fetched by
+    // scalar loads into scalar registers instead of every lane's registers.
+    typedef const __attribute__((address_space(4))) BatchOp ConstOp;
+    typedef const __attribute__((address_space(4))) int ConstInt;
+    ConstOp *cops = (ConstOp *)ops;
+    ConstInt *ctasks = (ConstInt *)tasks;
     for (int64_t q = blockIdx.x; q < ntasks; q += gridDim.x) {
-        const int2 t = tasks[q];
-        const BatchOp &op = ops[t.x];
+        const int2 t = make_int2(ctasks[2 * q], ctasks[2 * q + 1]);
+        const BatchOp &op = *(const BatchOp *)&cops[t.x];
         if (op.kind == WS_OP_GEMM) {
             const int32_t tm = t.y / op.g.tiles_n, tn = t.y % op.g.tiles_n;
             if (op.centre) {
@@ -915,6 +922,13 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchOp *ops, const in
         }
         __syncthreads();   // LDS is reused by the next task
     }
+}
+
+int batch_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_kernel, 256, 0) != hipSuccess || n < 1)
+        n = 2;
+    return n;
 }
 
 hipError_t launch_batch(const BatchOp *ops, const int2 *tasks, int64_t ntasks, int grid,

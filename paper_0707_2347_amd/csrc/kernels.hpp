@@ -43,6 +43,9 @@ void fill_batch_op(BatchOp &b, const ws_op_desc &op, const DevBufs &bufs, int64_
 
 // One persistent launch over the independent tasks of one phase: workgroup w
 // of `grid` runs tasks w, w + grid, ...
+// Resident workgroups of the batch kernel per CU (its persistent grid is
+// this many per CU).
+int batch_blocks_per_cu();
 hipError_t launch_batch(const BatchOp *ops, const int2 *tasks, int64_t ntasks, int grid,
                         hipStream_t stream);
 
