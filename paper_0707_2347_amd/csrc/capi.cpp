@@ -158,16 +158,24 @@ static void fill_stats(const Plan &plan, const ws_args &a, ws_stats &s) {
 int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, bool trace,
              void *scratch, size_t scratch_bytes) {
     DevBufs bufs{{a.A, a.B, a.C, ws}, scratch, scratch_bytes};
+    // Traced runs: a start/stop event pair per operation, stamped by the
+    // kernel dispatches themselves.
     std::vector<hipEvent_t> ev;
     if (trace) {
-        ev.resize(plan.ops.size() + 1);
+        ev.assign(2 * plan.ops.size(), nullptr);
         for (auto &e : ev)
-            if (hipEventCreate(&e) != hipSuccess)
+            if (hipEventCreate(&e) != hipSuccess) {
+                for (auto &d : ev)
+                    if (d)
+                        (void)hipEventDestroy(d);
                 return fail(WS_EHIP, "hipEventCreate failed");
-        (void)hipEventRecord(ev[0], stream);
+            }
     }
-    for (size_t i = 0; i < plan.ops.size(); ++i) {
+    int rc = WS_OK;
+    for (size_t i = 0; i < plan.ops.size() && rc == WS_OK; ++i) {
         const OpDesc &op = plan.ops[i];
+        if (trace)
+            launch_timing() = LaunchTiming{ev[2 * i], ev[2 * i + 1], false};
         hipError_t err;
         if (op.kind == WS_OP_ADD)
             err = launch_add(op, bufs, a.dtype, a.p, stream);
@@ -176,16 +184,16 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
         else
             err = launch_gemm(op, bufs, a.dtype, a.p, stream);
         if (err != hipSuccess)
-            return fail(WS_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(err));
-        if (trace)
-            (void)hipEventRecord(ev[i + 1], stream);
+            rc = fail(WS_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(err));
     }
+    launch_timing() = LaunchTiming{};
     if (trace) {
-        if (hipEventSynchronize(ev.back()) != hipSuccess)
-            return fail(WS_EHIP, "hipEventSynchronize failed");
-        for (size_t i = 0; i < plan.ops.size(); ++i) {
+        if (rc == WS_OK && hipStreamSynchronize(stream) != hipSuccess)
+            rc = fail(WS_EHIP, "hipStreamSynchronize failed");
+        for (size_t i = 0; i < plan.ops.size() && rc == WS_OK; ++i) {
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) != hipSuccess)
+                ms = 0.f;   // an operation with no kernel (empty view)
             const OpDesc &op = plan.ops[i];
             if (op.kind == WS_OP_ADD) {
                 g_trace.add_launches += 1;
@@ -201,7 +209,7 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
         for (auto &e : ev)
             (void)hipEventDestroy(e);
     }
-    return WS_OK;
+    return rc;
 }
 
 int execute(const ws_args &a, const PlanKey &key) {

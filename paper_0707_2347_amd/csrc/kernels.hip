@@ -12,6 +12,11 @@
 
 namespace wsmul {
 
+LaunchTiming &launch_timing() {
+    static thread_local LaunchTiming t;
+    return t;
+}
+
 // ===================================================================== adds
 // One launch executes a group of consecutive addition rows of a schedule:
 // for every element position, out[o] <- sum_i coef[o][i] * in[i] (mod p).
@@ -90,7 +95,7 @@ static hipError_t launch_lin_items(const LinParams &P, int nin, hipStream_t s) {
     const dim3 grid((threads + 255) / 256), block(256);
     switch (nin) {
 #define WS_LIN_CASE(N) \
-    case N: hipLaunchKernelGGL((lincomb_kernel<T, VEC, N, ITEMS>), grid, block, 0, s, P); break;
+    case N: ws_launch((lincomb_kernel<T, VEC, N, ITEMS>), grid, block, 0, s, P); break;
         WS_LIN_CASE(1) WS_LIN_CASE(2) WS_LIN_CASE(3) WS_LIN_CASE(4)
         WS_LIN_CASE(5) WS_LIN_CASE(6) WS_LIN_CASE(7) WS_LIN_CASE(8)
 #undef WS_LIN_CASE
@@ -726,22 +731,22 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
         P.tiles_n = (int32_t)((P.N + 127) / 128);
         const dim3 grid((uint32_t)big), block(256);
         if (centre) {
-            if (vec2) hipLaunchKernelGGL((gemm_lds_kernel<T, 128, 128, true, true>), grid, block, 0, s, P);
-            else hipLaunchKernelGGL((gemm_lds_kernel<T, 128, 128, true, false>), grid, block, 0, s, P);
+            if (vec2) ws_launch((gemm_lds_kernel<T, 128, 128, true, true>), grid, block, 0, s, P);
+            else ws_launch((gemm_lds_kernel<T, 128, 128, true, false>), grid, block, 0, s, P);
         } else {
-            if (vec2) hipLaunchKernelGGL((gemm_lds_kernel<T, 128, 128, false, true>), grid, block, 0, s, P);
-            else hipLaunchKernelGGL((gemm_lds_kernel<T, 128, 128, false, false>), grid, block, 0, s, P);
+            if (vec2) ws_launch((gemm_lds_kernel<T, 128, 128, false, true>), grid, block, 0, s, P);
+            else ws_launch((gemm_lds_kernel<T, 128, 128, false, false>), grid, block, 0, s, P);
         }
     } else if (mid >= 256) {
         P.tiles_m = (int32_t)((P.M + 63) / 64);
         P.tiles_n = (int32_t)((P.N + 63) / 64);
         const dim3 grid((uint32_t)mid), block(256);
         if (centre) {
-            if (vec2) hipLaunchKernelGGL((gemm_lds_kernel<T, 64, 64, true, true>), grid, block, 0, s, P);
-            else hipLaunchKernelGGL((gemm_lds_kernel<T, 64, 64, true, false>), grid, block, 0, s, P);
+            if (vec2) ws_launch((gemm_lds_kernel<T, 64, 64, true, true>), grid, block, 0, s, P);
+            else ws_launch((gemm_lds_kernel<T, 64, 64, true, false>), grid, block, 0, s, P);
         } else {
-            if (vec2) hipLaunchKernelGGL((gemm_lds_kernel<T, 64, 64, false, true>), grid, block, 0, s, P);
-            else hipLaunchKernelGGL((gemm_lds_kernel<T, 64, 64, false, false>), grid, block, 0, s, P);
+            if (vec2) ws_launch((gemm_lds_kernel<T, 64, 64, false, true>), grid, block, 0, s, P);
+            else ws_launch((gemm_lds_kernel<T, 64, 64, false, false>), grid, block, 0, s, P);
         }
     } else if (P.M % 32 == 0 && P.N % 32 == 0 && P.K % 64 == 0 && P.K > 0 && P.lda % 2 == 0 &&
                P.ldb % 2 == 0 && aligned16(P.A) && aligned16(P.B)) {
@@ -751,19 +756,19 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
         P.tiles_m = (int32_t)(P.M / 32);
         P.tiles_n = (int32_t)(P.N / 32);
         const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(64 * W);
-        if (c2) hipLaunchKernelGGL((gemm_dma_kernel<T, true, W, ST, SK>), grid, block, 0, s, P);
-        else hipLaunchKernelGGL((gemm_dma_kernel<T, false, W, ST, SK>), grid, block, 0, s, P);
+        if (c2) ws_launch((gemm_dma_kernel<T, true, W, ST, SK>), grid, block, 0, s, P);
+        else ws_launch((gemm_dma_kernel<T, false, W, ST, SK>), grid, block, 0, s, P);
     } else {
         P.tiles_m = (int32_t)((P.M + 31) / 32);
         P.tiles_n = (int32_t)((P.N + 31) / 32);
         const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(64 * WS_SK_WAVES);
         const bool v4 = vec2 && (P.K % 4 == 0);
         if (centre) {
-            if (v4) hipLaunchKernelGGL((gemm_sk_kernel<T, true, true, WS_SK_WAVES>), grid, block, 0, s, P);
-            else hipLaunchKernelGGL((gemm_sk_kernel<T, true, false, WS_SK_WAVES>), grid, block, 0, s, P);
+            if (v4) ws_launch((gemm_sk_kernel<T, true, true, WS_SK_WAVES>), grid, block, 0, s, P);
+            else ws_launch((gemm_sk_kernel<T, true, false, WS_SK_WAVES>), grid, block, 0, s, P);
         } else {
-            if (v4) hipLaunchKernelGGL((gemm_sk_kernel<T, false, true, WS_SK_WAVES>), grid, block, 0, s, P);
-            else hipLaunchKernelGGL((gemm_sk_kernel<T, false, false, WS_SK_WAVES>), grid, block, 0, s, P);
+            if (v4) ws_launch((gemm_sk_kernel<T, false, true, WS_SK_WAVES>), grid, block, 0, s, P);
+            else ws_launch((gemm_sk_kernel<T, false, false, WS_SK_WAVES>), grid, block, 0, s, P);
         }
     }
     return hipGetLastError();
@@ -839,10 +844,10 @@ hipError_t launch_range_check(const void *ptr, int64_t rows, int64_t cols, int64
     const int64_t total = rows * cols;
     const uint32_t blocks = (uint32_t)std::min<int64_t>((total + 255) / 256, 4096);
     if (dtype == WS_I64)
-        hipLaunchKernelGGL(range_check_kernel<int64_t>, dim3(blocks), dim3(256), 0, stream,
+        ws_launch(range_check_kernel<int64_t>, dim3(blocks), dim3(256), 0, stream,
                            static_cast<const int64_t *>(ptr), rows, cols, ld, (double)p, flag);
     else
-        hipLaunchKernelGGL(range_check_kernel<double>, dim3(blocks), dim3(256), 0, stream,
+        ws_launch(range_check_kernel<double>, dim3(blocks), dim3(256), 0, stream,
                            static_cast<const double *>(ptr), rows, cols, ld, (double)p, flag);
     return hipGetLastError();
 }
@@ -936,7 +941,7 @@ hipError_t launch_batch(const BatchOp *ops, const int2 *tasks, int64_t ntasks, i
     if (ntasks == 0)
         return hipSuccess;
     const int g = (int)std::min<int64_t>(grid, ntasks);
-    hipLaunchKernelGGL(batch_kernel, dim3(g), dim3(256), 0, stream, ops, tasks, ntasks);
+    ws_launch(batch_kernel, dim3(g), dim3(256), 0, stream, ops, tasks, ntasks);
     return hipGetLastError();
 }
 

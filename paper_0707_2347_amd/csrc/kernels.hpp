@@ -1,12 +1,35 @@
 // Host-side launchers of the device kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "gemm_common.hpp"
 #include "wsmul.h"
 
 namespace wsmul {
+
+// Kernel timing of traced runs.  While `start`/`stop` are set, the launches
+// of this thread stamp `start` when the first kernel begins and `stop` when
+// the last one ends: the dispatch records them, so the interval is the
+// kernels' own execution time, as a kernel-trace profiler reports it.
+struct LaunchTiming {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool started = false;
+};
+LaunchTiming &launch_timing();
+
+template <typename F, typename... Args>
+inline void ws_launch(F kernel, const dim3 &grid, const dim3 &block, uint32_t shmem, hipStream_t s,
+                      Args... args) {
+    LaunchTiming &t = launch_timing();
+    hipEvent_t first = nullptr;
+    if (t.start && !t.started) {
+        first = t.start;
+        t.started = true;
+    }
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, first, t.stop, 0u, args...);
+}
 
 // Base pointers of the four buffers a plan refers to (WS_BUF_A .. WS_BUF_W).
 struct DevBufs {
@@ -41,11 +64,12 @@ struct BatchOp {
 
 void fill_batch_op(BatchOp &b, const ws_op_desc &op, const DevBufs &bufs, int64_t p);
 
-// One persistent launch over the independent tasks of one phase: workgroup w
-// of `grid` runs tasks w, w + grid, ...
 // Resident workgroups of the batch kernel per CU (its persistent grid is
 // this many per CU).
 int batch_blocks_per_cu();
+
+// One persistent launch over the independent tasks of one phase: workgroup w
+// of `grid` runs tasks w, w + grid, ...
 hipError_t launch_batch(const BatchOp *ops, const int2 *tasks, int64_t ntasks, int grid,
                         hipStream_t stream);
 

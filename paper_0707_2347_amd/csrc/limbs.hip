@@ -282,17 +282,17 @@ hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtyp
     const uint32_t blocks_a = (uint32_t)((D.Mp * (D.Kp / 8) + 255) / 256);
     const dim3 grid_b((uint32_t)(D.Kp / 64), (uint32_t)(D.Np / 64));
     if (dtype == WS_I64) {
-        hipLaunchKernelGGL(split_rows_kernel<int64_t>, dim3(blocks_a), dim3(256), 0, stream,
+        ws_launch(split_rows_kernel<int64_t>, dim3(blocks_a), dim3(256), 0, stream,
                            static_cast<const int64_t *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
                            P.p, P.half);
-        hipLaunchKernelGGL(split_cols_kernel<int64_t>, grid_b, dim3(256), 0, stream,
+        ws_launch(split_cols_kernel<int64_t>, grid_b, dim3(256), 0, stream,
                            static_cast<const int64_t *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
                            P.p, P.half);
     } else {
-        hipLaunchKernelGGL(split_rows_kernel<double>, dim3(blocks_a), dim3(256), 0, stream,
+        ws_launch(split_rows_kernel<double>, dim3(blocks_a), dim3(256), 0, stream,
                            static_cast<const double *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
                            P.p, P.half);
-        hipLaunchKernelGGL(split_cols_kernel<double>, grid_b, dim3(256), 0, stream,
+        ws_launch(split_cols_kernel<double>, grid_b, dim3(256), 0, stream,
                            static_cast<const double *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
                            P.p, P.half);
     }
@@ -303,9 +303,9 @@ hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtyp
     P.tiles_n = (int32_t)(D.Np / TILE);
     const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(256);
     if (dtype == WS_I64)
-        hipLaunchKernelGGL(gemm_digits_kernel<int64_t>, grid, block, 0, stream, D);
+        ws_launch(gemm_digits_kernel<int64_t>, grid, block, 0, stream, D);
     else
-        hipLaunchKernelGGL(gemm_digits_kernel<double>, grid, block, 0, stream, D);
+        ws_launch(gemm_digits_kernel<double>, grid, block, 0, stream, D);
     return hipGetLastError();
 }
 
