@@ -6,7 +6,7 @@
 //   base products, binary64 matrix cores: 58 TFLOP/s for the 128 x 128 tile
 //     class (x0.87 when the accumulators must be folded), 30 TFLOP/s for the
 //     64 x 64 class, 19 TFLOP/s for the split-K class, 8 us floor per launch;
-//   base products, 8-bit digits: 215 / 190 / 140 / 100 / 40 TFLOP/s
+//   base products, 8-bit digits: 300 / 265 / 180 / 120 / 40 TFLOP/s
 //     (equivalent) by 128 x 128 tile count, plus the digit split passes
 //     (bytes at 5 TB/s);
 //   addition groups: bytes moved at 4.5 TB/s, 4 us floor per launch.
@@ -40,10 +40,10 @@ double gemm_f64_us(int64_t M, int64_t N, int64_t K, int64_t p) {
 double gemm_digits_us(int64_t M, int64_t N, int64_t K) {
     const double flops = 2.0 * (double)M * (double)N * (double)K;
     const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
-    const double rate = tiles >= 8192   ? 215e12
-                        : tiles >= 2048 ? 190e12
-                        : tiles >= 512  ? 140e12
-                        : tiles >= 128  ? 100e12
+    const double rate = tiles >= 8192   ? 300e12
+                        : tiles >= 2048 ? 265e12
+                        : tiles >= 512  ? 180e12
+                        : tiles >= 128  ? 120e12
                                         : 40e12;
     const double split_bytes = 11.0 * ((double)M * (double)K + (double)K * (double)N);
     return std::max(8.0, flops / rate * 1e6) + 2.0 * 5.0 + split_bytes / 5e12 * 1e6;

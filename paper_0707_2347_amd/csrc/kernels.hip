@@ -845,10 +845,10 @@ hipError_t launch_range_check(const void *ptr, int64_t rows, int64_t cols, int64
     const uint32_t blocks = (uint32_t)std::min<int64_t>((total + 255) / 256, 4096);
     if (dtype == WS_I64)
         ws_launch(range_check_kernel<int64_t>, dim3(blocks), dim3(256), 0, stream,
-                           static_cast<const int64_t *>(ptr), rows, cols, ld, (double)p, flag);
+                  static_cast<const int64_t *>(ptr), rows, cols, ld, (double)p, flag);
     else
         ws_launch(range_check_kernel<double>, dim3(blocks), dim3(256), 0, stream,
-                           static_cast<const double *>(ptr), rows, cols, ld, (double)p, flag);
+                  static_cast<const double *>(ptr), rows, cols, ld, (double)p, flag);
     return hipGetLastError();
 }
 

@@ -13,6 +13,10 @@
 // Digits are first written to a scratch area as three int8 planes per
 // operand, each R x Kp with the inner dimension contiguous (B transposed),
 // rows padded to the 128-row tile and Kp to the 64-wide K-step with zeros.
+// A plane is stored tile by tile in the order the product consumes it: the
+// 128 x 64 block of row-tile i and K-step t is 8 KB at ((i * Kp/64) + t) * 8K,
+// rows of 64 bytes, with the 16-byte chunks of each row XOR-swizzled exactly
+// as the product's LDS tiles are, so that every load copies contiguous bytes.
 #include "gemm_common.hpp"
 #include "wsmul_internal.hpp"
 
@@ -27,6 +31,14 @@ constexpr int KSTEP = 64;     // inner dimension per matrix-core op
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
+// Byte offset of digit (r, k) in a tiled plane of Kp columns.
+__device__ __forceinline__ int64_t tiled_pos(int64_t r, int64_t k, int64_t Kp) {
+    const int64_t rt = r / TILE, kt = k / KSTEP;
+    const int rr = (int)(r % TILE), kk = (int)(k % KSTEP);
+    const int chunk = (kk >> 4) ^ ((rr >> 2) & 3);
+    return (rt * (Kp / KSTEP) + kt) * (TILE * KSTEP) + rr * KSTEP + chunk * 16 + (kk & 15);
+}
+
 __device__ __forceinline__ void digits3(double x, double p, double half, int8_t &d0, int8_t &d1,
                                         int8_t &d2) {
     const int32_t c = (int32_t)(x > half ? x - p : x);
@@ -39,7 +51,8 @@ __device__ __forceinline__ void digits3(double x, double p, double half, int8_t 
     d2 = (int8_t)c2;
 }
 
-// A (R x K, row-major) -> planes[d][r][k]; 8 consecutive k per thread.
+// A (R x K, row-major) -> tiled planes of digits (r, k); 8 consecutive k per
+// thread.
 template <typename T>
 __global__ __launch_bounds__(256) void split_rows_kernel(const T *X, int64_t ld, int64_t R,
                                                          int64_t K, int64_t Rp, int64_t Kp,
@@ -59,14 +72,14 @@ __global__ __launch_bounds__(256) void split_rows_kernel(const T *X, int64_t ld,
         const double x = (r < R && k < K) ? to_f64(X[r * ld + k]) : 0.0;
         digits3(x, p, half, o0.b[t], o1.b[t], o2.b[t]);
     }
-    const int64_t plane = Rp * Kp;
-    *reinterpret_cast<uint64_t *>(planes + r * Kp + k0) = o0.u;
-    *reinterpret_cast<uint64_t *>(planes + plane + r * Kp + k0) = o1.u;
-    *reinterpret_cast<uint64_t *>(planes + 2 * plane + r * Kp + k0) = o2.u;
+    const int64_t plane = Rp * Kp, at = tiled_pos(r, k0, Kp);
+    *reinterpret_cast<uint64_t *>(planes + at) = o0.u;
+    *reinterpret_cast<uint64_t *>(planes + plane + at) = o1.u;
+    *reinterpret_cast<uint64_t *>(planes + 2 * plane + at) = o2.u;
 }
 
-// B (K x N, row-major) -> planes[d][n][k] (transposed through LDS in 64 x 64
-// tiles so that both the reads and the writes are contiguous).
+// B (K x N, row-major) -> tiled planes of digits (n, k), transposed through
+// LDS in 64 x 64 tiles so that both the reads and the writes are contiguous.
 template <typename T>
 __global__ __launch_bounds__(256) void split_cols_kernel(const T *X, int64_t ld, int64_t K,
                                                          int64_t N, int64_t Np, int64_t Kp,
@@ -96,7 +109,7 @@ __global__ __launch_bounds__(256) void split_cols_kernel(const T *X, int64_t ld,
         const int64_t n = n0 + nn;
         if (n < Np && k0 + 16 * part < Kp) {
             const uint4 v = *reinterpret_cast<const uint4 *>(&tile[d][nn][16 * part]);
-            *reinterpret_cast<uint4 *>(planes + d * plane + n * Kp + k0 + 16 * part) = v;
+            *reinterpret_cast<uint4 *>(planes + d * plane + tiled_pos(n, k0 + 16 * part, Kp)) = v;
         }
     }
 }
@@ -111,40 +124,57 @@ struct DigitParams {
     double cw[5];              // 2^(8w) mod p
 };
 
-// 128 x 128 output tile, four waves in a 2 x 2 grid (64 x 64 each, one wave
-// per SIMD so that the five int32 accumulator sets -- one per weight class,
-// 320 registers -- fit), digit tiles of 64 inner elements double-buffered in
-// LDS and filled by direct global-to-LDS loads issued one K-step ahead (no
-// staging registers).  A load instruction places lane l's 16 bytes at
-// base + 16*l, so each instruction fills 16 rows of 64 bytes; within a row
-// the four 16-byte chunks are stored XOR-swizzled (chunk c of row r at slot
-// c ^ ((r >> 2) & 3)) so that the 16 lanes reading one chunk of 16
-// consecutive rows hit 16 distinct slots of the 256 LDS bytes they span.
-template <typename T>
-__global__ __launch_bounds__(256) void gemm_digits_kernel(DigitParams D) {
+// 128 x 128 output tile per workgroup, 2 x WN waves (wave tiles of 64 x
+// 128/WN: with WN = 4 the five int32 accumulator sets, one per weight class,
+// take 160 registers and two waves share each SIMD), digit tiles of 64 inner
+// elements in STAGES LDS buffers filled by direct global-to-LDS loads issued
+// STAGES-1 K-steps ahead (no staging registers).  A load instruction places
+// lane l's 16 bytes at base + 16*l; the planes are tiled and swizzled so that
+// each instruction copies 1 KB of contiguous bytes, and within a 64-byte row
+// the 16-byte chunk c of row r sits at slot c ^ ((r >> 2) & 3), so the 16
+// lanes reading one chunk of 16 consecutive rows hit 16 distinct slots of the
+// 256 LDS bytes they span.
+#ifndef WS_I8_WN
+#define WS_I8_WN 4
+#endif
+#ifndef WS_I8_STAGES
+#define WS_I8_STAGES 2
+#endif
+template <typename T, int WN, int STAGES>
+__global__ __launch_bounds__(128 * WN) void gemm_digits_kernel(DigitParams D) {
     constexpr int PLANE = TILE * KSTEP;                     // bytes of one digit tile
-    __shared__ __attribute__((aligned(16))) int8_t lds[2][2][3][PLANE];   // [stage][A|B][digit]
+    constexpr int WAVES = 2 * WN, NT = 64 * WAVES;
+    constexpr int WCOLS = TILE / WN, JB = WCOLS / 16;       // wave tile columns, 16-column blocks
+    constexpr int LPW = 48 / WAVES;                         // load instructions per wave and K-step
+    static_assert(STAGES == 2 || STAGES == 3, "two or three buffers");
+    static_assert(LPW == 6 || LPW == 12, "four or eight waves");
+    // [stage][A|B][digit], sized for three buffers whatever STAGES is: with a
+    // template-dependent extent the host compiler drops the kernel's launch
+    // stub without a diagnostic.
+    __shared__ __attribute__((aligned(16))) int8_t lds[3][2][3][PLANE];
     const GemmParams &P = D.g;
     int32_t tm, tn;
     tile_of(P.tiles_m, P.tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * TILE, n0 = (int64_t)tn * TILE;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;       // 2 x 2 waves
+    const int wm = wave / WN, wn = wave % WN;
     const int li = lane & 15, g = lane >> 4;
     const int64_t plA = D.Mp * D.Kp, plB = D.Np * D.Kp;
 
     // 48 load instructions per K-step (2 operands x 3 digits x 8 blocks of
-    // 16 rows), twelve per wave.
-    auto issue = [&](int st, int64_t k0) {
+    // 16 rows), LPW per wave.  The planes are tiled (one contiguous, already
+    // swizzled 8 KB block per row-tile and K-step), so instruction blk of a
+    // block copies its bytes blk*1024 .. blk*1024 + 1023 to the same LDS
+    // offsets.
+    const int64_t ksteps = D.Kp / KSTEP;
+    auto issue = [&](int st, int64_t t) {
 #pragma unroll
-        for (int j = 0; j < 12; ++j) {
-            const int i = wave + 4 * j;
+        for (int j = 0; j < LPW; ++j) {
+            const int i = wave + WAVES * j;
             const int op = i / 24, d = (i % 24) / 8, blk = i % 8;
-            const int row = blk * 16 + (lane >> 2), slot = lane & 3;
-            const int chunk = slot ^ ((row >> 2) & 3);
-            const int8_t *src = op == 0 ? D.Ad + d * plA + (m0 + row) * D.Kp
-                                        : D.Bd + d * plB + (n0 + row) * D.Kp;
-            __builtin_amdgcn_global_load_lds(src + k0 + 16 * chunk, &lds[st][op][d][blk * 1024], 16, 0, 0);
+            const int8_t *src = op == 0 ? D.Ad + d * plA + ((int64_t)tm * ksteps + t) * PLANE
+                                        : D.Bd + d * plB + ((int64_t)tn * ksteps + t) * PLANE;
+            __builtin_amdgcn_global_load_lds(src + blk * 1024 + 16 * lane, &lds[st][op][d][blk * 1024], 16, 0, 0);
         }
     };
     auto frag = [&](int st, int op, int d, int row) {
@@ -152,30 +182,22 @@ __global__ __launch_bounds__(256) void gemm_digits_kernel(DigitParams D) {
             &lds[st][op][d][row * KSTEP + 16 * (g ^ ((row >> 2) & 3))]);
     };
 
-    i32x4 acc[5][4][4];
+    i32x4 acc[5][4][JB];
 #pragma unroll
     for (int w = 0; w < 5; ++w)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < JB; ++j)
                 acc[w][i][j] = i32x4{0, 0, 0, 0};
 
-    const int64_t ksteps = D.Kp / KSTEP;
-    if (ksteps > 0)
-        issue(0, 0);
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    for (int64_t t = 0; t < ksteps; ++t) {
-        const int cur = (int)(t & 1);
-        if (t + 1 < ksteps)
-            issue(cur ^ 1, (t + 1) * KSTEP);
+    auto compute = [&](int cur) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            i32x4 bf[4];
+            i32x4 bf[JB];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                bf[j] = frag(cur, 1, b, wn * 64 + j * 16 + li);
+            for (int j = 0; j < JB; ++j)
+                bf[j] = frag(cur, 1, b, wn * WCOLS + j * 16 + li);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 i32x4 af[4];
@@ -185,12 +207,46 @@ __global__ __launch_bounds__(256) void gemm_digits_kernel(DigitParams D) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
+                    for (int j = 0; j < JB; ++j)
                         acc[a + b][i][j] =
                             __builtin_amdgcn_mfma_i32_16x16x64_i8(af[i], bf[j], acc[a + b][i][j], 0, 0, 0);
             }
         }
-        __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of the next K-step have landed
+    };
+
+    if (STAGES == 2) {
+        if (ksteps > 0)
+            issue(0, 0);
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        for (int64_t t = 0; t < ksteps; ++t) {
+            const int cur = (int)(t & 1);
+            if (t + 1 < ksteps)
+                issue(cur ^ 1, t + 1);
+            compute(cur);
+            __builtin_amdgcn_s_waitcnt(0);   // this wave's loads of the next K-step have landed
+            __syncthreads();
+        }
+    } else {
+        if (ksteps > 0)
+            issue(0, 0);
+        if (ksteps > 1)
+            issue(1, 1);
+        for (int64_t t = 0; t < ksteps; ++t) {
+            // This wave's loads of step t have landed (only step t+1's may
+            // still be in flight), then every wave's, and every wave is done
+            // with step t-1: a plain barrier with no fence, so that the loads
+            // of step t+1 stay in flight across it.
+            if (t + 1 < ksteps) {
+                if (LPW == 6) asm volatile("s_waitcnt vmcnt(6)\n\ts_barrier" ::: "memory");
+                else asm volatile("s_waitcnt vmcnt(12)\n\ts_barrier" ::: "memory");
+            } else {
+                asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+            }
+            if (t + 2 < ksteps)
+                issue((int)((t + 2) % 3), t + 2);
+            compute((int)(t % 3));
+        }
         __syncthreads();
     }
 
@@ -205,7 +261,7 @@ __global__ __launch_bounds__(256) void gemm_digits_kernel(DigitParams D) {
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < JB; ++j)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         double s = 0.0;
@@ -213,11 +269,11 @@ __global__ __launch_bounds__(256) void gemm_digits_kernel(DigitParams D) {
                         for (int w = 0; w < 5; ++w)
                             s = fma(D.cw[w], mod_reduce((double)acc[w][i][j][v], P.p, P.pinv), s);
                         const int r = i * 16 + 4 * g + v;
-                        stage[r * TILE + wn * 64 + j * 16 + li] = product_residue(P, s);
+                        stage[r * TILE + wn * WCOLS + j * 16 + li] = product_residue(P, s);
                     }
         }
         __syncthreads();
-        for (int e = tid; e < 64 * TILE; e += 256) {
+        for (int e = tid; e < 64 * TILE; e += NT) {
             const int r = e / TILE, c = e % TILE;
             const int64_t row = m0 + h * 64 + r, col = n0 + c;
             if (row < P.M && col < P.N)
@@ -283,29 +339,30 @@ hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtyp
     const dim3 grid_b((uint32_t)(D.Kp / 64), (uint32_t)(D.Np / 64));
     if (dtype == WS_I64) {
         ws_launch(split_rows_kernel<int64_t>, dim3(blocks_a), dim3(256), 0, stream,
-                           static_cast<const int64_t *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
-                           P.p, P.half);
+                  static_cast<const int64_t *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
+                  P.p, P.half);
         ws_launch(split_cols_kernel<int64_t>, grid_b, dim3(256), 0, stream,
-                           static_cast<const int64_t *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
-                           P.p, P.half);
+                  static_cast<const int64_t *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
+                  P.p, P.half);
     } else {
         ws_launch(split_rows_kernel<double>, dim3(blocks_a), dim3(256), 0, stream,
-                           static_cast<const double *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
-                           P.p, P.half);
+                  static_cast<const double *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
+                  P.p, P.half);
         ws_launch(split_cols_kernel<double>, grid_b, dim3(256), 0, stream,
-                           static_cast<const double *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
-                           P.p, P.half);
+                  static_cast<const double *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
+                  P.p, P.half);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     P.tiles_m = (int32_t)(D.Mp / TILE);
     P.tiles_n = (int32_t)(D.Np / TILE);
-    const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(256);
+    constexpr int WN = WS_I8_WN, ST = WS_I8_STAGES;
+    const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(128 * WN);
     if (dtype == WS_I64)
-        ws_launch(gemm_digits_kernel<int64_t>, grid, block, 0, stream, D);
+        ws_launch(gemm_digits_kernel<int64_t, WN, ST>, grid, block, 0, stream, D);
     else
-        ws_launch(gemm_digits_kernel<double>, grid, block, 0, stream, D);
+        ws_launch(gemm_digits_kernel<double, WN, ST>, grid, block, 0, stream, D);
     return hipGetLastError();
 }
 
