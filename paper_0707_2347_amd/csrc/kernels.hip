@@ -496,15 +496,15 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_sk_kernel(GemmParams P) {
     }
 }
 
-// Base products whose shape is whole 32 x 32 output tiles and 64-deep
-// inner chunks with 16-byte aligned rows (every Winograd leaf of a
-// power-of-two product): one 32 x 32 output tile per workgroup over the full
-// inner dimension, split among the waves.  Wave w owns the SK-deep
-// sub-chunks w, w + WAVES, w + 2*WAVES, ... of the inner dimension; it
-// streams their A (32 x SK) and B (SK x 32) blocks into STAGES private LDS
-// buffers by direct global-to-LDS loads, waits on its own load counter and
-// needs no workgroup barrier until the partial tiles are summed in LDS
-// before the fused epilogue.
+// Base products whose shape is whole TM x TM output tiles (TM = 32 or 64)
+// and 64-deep inner chunks with 16-byte aligned rows (every Winograd leaf of a
+// power-of-two product): one TM x TM output tile per workgroup over the full
+// inner dimension, split among the waves.  Wave w owns the SK-deep sub-chunks
+// w, w + WAVES, w + 2*WAVES, ... of the inner dimension; it streams their A
+// (TM x SK) and B (SK x TM) blocks into STAGES private LDS buffers by direct
+// global-to-LDS loads, waits on its own load counter and needs no workgroup
+// barrier until the partial tiles are summed in LDS before the fused
+// epilogue.
 //
 // A load instruction writes lane l's 16 bytes at base + 16*l, so the LDS
 // layout is fixed by the instruction and the permutation lives in the global
@@ -519,9 +519,17 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_sk_kernel(GemmParams P) {
 #ifndef WS_DMA_SK
 #define WS_DMA_SK 16
 #endif
+#ifndef WS_DMA64_WAVES
+#define WS_DMA64_WAVES 8
+#endif
+#ifndef WS_DMA64_STAGES
+#define WS_DMA64_STAGES 2
+#endif
+#ifndef WS_DMA64_SK
+#define WS_DMA64_SK 8
+#endif
 namespace dmak {
-constexpr int TM = 32;
-// Piece swizzles: A-rows of SK*8 bytes, B-rows of 256 bytes.
+// Piece swizzles: A-rows of SK*8 bytes, B-rows of TM*8 bytes.
 template <int SK>
 __device__ __forceinline__ int aswz(int r) {
     return SK == 16 ? ((r & 7) ^ ((r >> 3) & 1)) : (((r >> 2) & 3) ^ (((r >> 1) & 1) << 1));
@@ -546,23 +554,28 @@ struct alignas(16) Pair {
     T x, y;
 };
 
-template <typename T, bool CENTRE, int WAVES, int STAGES, int SK>
+template <typename T, bool CENTRE, int TM, int WAVES, int STAGES, int SK>
 __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
     using namespace dmak;
-    constexpr int NT = 64 * WAVES;
-    constexpr int EPT = TM * TM / NT;
-    constexpr int S = SK / 4;                        // matrix-core steps per sub-chunk
+    constexpr int NB = TM / 16;                        // 16 x 16 blocks per tile side
+    constexpr int NT = 64 * WAVES, EPT = TM * TM / NT;
+    constexpr int S = SK / 4;                          // matrix-core steps per sub-chunk
     constexpr int A_BYTES = TM * SK * 8, SUB_BYTES = 2 * A_BYTES;
-    constexpr int AROWS = 1024 / (SK * 8);           // A-rows per load instruction
-    constexpr int AI = TM / AROWS, BI = SK / 4;      // load instructions for A, for B
-    constexpr int LPS = AI + BI;                     // per sub-chunk
-    // Rows of the partial tiles padded by two when the buffers have room.
-    constexpr int PROW = WAVES * TM * (TM + 2) * 8 <= WAVES * STAGES * SUB_BYTES ? TM + 2 : TM;
+    constexpr int AROWS = 1024 / (SK * 8), AI = TM / AROWS;   // A: rows per instruction, instructions
+    constexpr int BPR = TM / 2, BROWS = 64 / BPR, BI = SK / BROWS;   // B: pieces per row, rows, instructions
+    constexpr int LPS = AI + BI;                       // load instructions per sub-chunk
+    constexpr int LDS_BYTES = WAVES * STAGES * SUB_BYTES;
+    constexpr bool PREFETCH = EPT <= 2;                // epilogue inputs fetched up front
+    // Partial tiles for the split-K sum, rows padded by two when there is
+    // room; PW of them fit the buffers at once (all, or half the waves').
+    constexpr int PROW = WAVES * TM * (TM + 2) * 8 <= LDS_BYTES ? TM + 2 : TM;
     constexpr int PSTRIDE = TM * PROW;
+    constexpr int PW = WAVES * PSTRIDE * 8 <= LDS_BYTES ? WAVES : WAVES / 2;
+    static_assert(TM == 32 || TM == 64, "32 or 64");
     static_assert(SK == 8 || SK == 16, "sub-chunks of 8 or 16");
     static_assert(STAGES >= 2 && (STAGES - 2) * LPS <= 24, "load counter range");
-    static_assert(WAVES * PSTRIDE * 8 <= WAVES * STAGES * SUB_BYTES, "partials fit the buffers");
-    __shared__ __attribute__((aligned(16))) char lds[WAVES * STAGES * SUB_BYTES];
+    static_assert(PW * PSTRIDE * 8 <= LDS_BYTES, "partials fit the buffers");
+    __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
     int32_t tm, tn;
     tile_of(P.tiles_m, P.tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TM;
@@ -572,12 +585,15 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
     const char *B = static_cast<const char *>(P.B);
     char *mine = lds + wave * (STAGES * SUB_BYTES);
 
-    // Epilogue inputs do not depend on the product: fetch them first.
-    double ex[EPT][WS_MAX_IN];
+    // Small tiles: epilogue inputs do not depend on the product, fetch them
+    // first.
+    double ex[PREFETCH ? EPT : 1][WS_MAX_IN];
+    if (PREFETCH) {
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        const int e = tid + NT * u;
-        epilogue_load<T>(P, ex[u], m0 + e / TM, n0 + e % TM);
+        for (int u = 0; u < EPT; ++u) {
+            const int e = tid + NT * u;
+            epilogue_load<T>(P, ex[u], m0 + e / TM, n0 + e % TM);
+        }
     }
 
     const int64_t nsub = (P.K / SK - wave + WAVES - 1) / WAVES;   // this wave's sub-chunks
@@ -594,7 +610,7 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
         }
 #pragma unroll
         for (int j = 0; j < BI; ++j) {
-            const int k = 4 * j + (lane >> 4), piece = (lane & 15) ^ bswz<SK>(k);
+            const int k = BROWS * j + lane / BPR, piece = (lane % BPR) ^ bswz<SK>(k);
             __builtin_amdgcn_global_load_lds(B + ((k0 + k) * P.ldb + n0) * 8 + piece * 16,
                                              base + A_BYTES + j * 1024, 16, 0, 0);
         }
@@ -604,11 +620,11 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
         return (CENTRE && x > P.half) ? x - P.p : x;
     };
 
-    f64x4 acc[2][2];
+    f64x4 acc[NB][NB];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NB; ++j)
             acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
     int since_fold = 0;
 
@@ -625,9 +641,9 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
             issue((int)((u + STAGES - 1) % STAGES), u + STAGES - 1);
         const char *sa = mine + (int)(u % STAGES) * SUB_BYTES;
         const char *sb = sa + A_BYTES;
-        double a[2][S], b[2][S];
+        double a[NB][S], b[NB][S];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < NB; ++i) {
             const int r = 16 * i + li;
 #pragma unroll
             for (int h = 0; h < S / 2; ++h) {
@@ -638,7 +654,7 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
             }
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NB; ++j)
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int k = S * kq + s, col = 16 * j + li;
@@ -648,15 +664,15 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < NB; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < NB; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
         if (P.kc_tiles > 0 && ++since_fold == P.kc_tiles) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < NB; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < NB; ++j)
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
                         acc[i][j][v] = mod_reduce(acc[i][j][v], P.p, P.pinv);
@@ -664,32 +680,62 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
         }
     }
 
-    // Partial tiles through LDS, summed by every thread for its epilogue
-    // elements.  When the whole inner dimension fits below 2^53 the raw
-    // partials are summed and reduced once.  Output of the 16 x 16 x 4 op:
-    // lane l, element v is row l/16 + 4v, column l%16.
+    // Split-K sum through LDS, then every thread sums the parked partials of
+    // its epilogue elements.  When the whole inner dimension fits below 2^53
+    // the raw partials are summed and reduced once.  Output of the 16 x 16 x 4
+    // op: lane l, element v is row l/16 + 4v, column l%16.
     const double mx = CENTRE ? P.half + 1.0 : P.p - 1.0;
     const bool raw = P.kc_tiles == 0 && (double)P.K * mx * mx < 9.0e15;
-    __syncthreads();
     double *part = reinterpret_cast<double *>(lds);
+    auto park = [&](int slot) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+            for (int j = 0; j < NB; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                part[wave * PSTRIDE + (16 * i + kq + 4 * v) * PROW + 16 * j + li] =
-                    raw ? acc[i][j][v] : mod_reduce(acc[i][j][v], P.p, P.pinv);
+                for (int v = 0; v < 4; ++v)
+                    part[slot * PSTRIDE + (16 * i + kq + 4 * v) * PROW + 16 * j + li] =
+                        raw ? acc[i][j][v] : mod_reduce(acc[i][j][v], P.p, P.pinv);
+    };
+    __syncthreads();
+    if (PW == WAVES) {
+        park(wave);
+    } else {
+        // Two halves: the upper waves park their partials, the lower waves
+        // add them to their own and park the sums.
+        if (wave >= PW)
+            park(wave - PW);
+        __syncthreads();
+        if (wave < PW) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const double mine_v = raw ? acc[i][j][v] : mod_reduce(acc[i][j][v], P.p, P.pinv);
+                        acc[i][j][v] = mine_v + part[wave * PSTRIDE + (16 * i + kq + 4 * v) * PROW + 16 * j + li];
+                    }
+        }
+        __syncthreads();
+        if (wave < PW)
+            park(wave);
+    }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < EPT; ++u) {
         const int e = tid + NT * u;
         double sum = 0.0;
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w)
+        for (int w = 0; w < PW; ++w)
             sum += part[w * PSTRIDE + (e / TM) * PROW + e % TM];
-        ex[u][0] = product_residue(P, sum);
-        epilogue_store<T>(P, ex[u], m0 + e / TM, n0 + e % TM);
+        const double prod = product_residue(P, sum);
+        if (PREFETCH) {
+            ex[u][0] = prod;
+            epilogue_store<T>(P, ex[u], m0 + e / TM, n0 + e % TM);
+        } else {
+            epilogue_apply<T>(P, prod, m0 + e / TM, n0 + e % TM);
+        }
     }
 }
 
@@ -704,6 +750,19 @@ static int32_t fold_chunks(int64_t p, bool centre, int64_t K, int waves, int sk)
     if (t >= per_wave)
         return 0;
     return (int32_t)std::max(1.0, std::min(t, 1.0e9));
+}
+
+// Whether gemm_dma_kernel centres its operands.  Centring costs a few vector
+// ops per operand element on every sub-chunk; a fold costs a reduction of
+// every accumulator (TM^2/64 per lane).  Centre only when, uncentred, the
+// folds would come often enough to cost more.
+static bool dma_centre(int64_t p, int64_t K, int tm, int waves, int sk) {
+    const int32_t t = fold_chunks(p, false, K, waves, sk);
+    if (t == 0)
+        return false;
+    const double fold_ops = 12.0 * (double)(tm * tm / 64);
+    const double centre_ops = 4.0 * (double)(2 * (tm / 16) * (sk / 4));
+    return fold_ops / (double)t > centre_ops;
 }
 
 
@@ -737,6 +796,16 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
             if (vec2) ws_launch((gemm_lds_kernel<T, 128, 128, false, true>), grid, block, 0, s, P);
             else ws_launch((gemm_lds_kernel<T, 128, 128, false, false>), grid, block, 0, s, P);
         }
+    } else if (mid >= 256 && P.M % 64 == 0 && P.N % 64 == 0 && P.K % 64 == 0 && P.lda % 2 == 0 &&
+               P.ldb % 2 == 0 && aligned16(P.A) && aligned16(P.B)) {
+        constexpr int W = WS_DMA64_WAVES, ST = WS_DMA64_STAGES, SK = WS_DMA64_SK;
+        const bool c2 = dma_centre((int64_t)P.p, P.K, 64, W, SK);
+        P.kc_tiles = fold_chunks((int64_t)P.p, c2, P.K, W, SK);
+        P.tiles_m = (int32_t)(P.M / 64);
+        P.tiles_n = (int32_t)(P.N / 64);
+        const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(64 * W);
+        if (c2) ws_launch((gemm_dma_kernel<T, true, 64, W, ST, SK>), grid, block, 0, s, P);
+        else ws_launch((gemm_dma_kernel<T, false, 64, W, ST, SK>), grid, block, 0, s, P);
     } else if (mid >= 256) {
         P.tiles_m = (int32_t)((P.M + 63) / 64);
         P.tiles_n = (int32_t)((P.N + 63) / 64);
@@ -751,13 +820,13 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
     } else if (P.M % 32 == 0 && P.N % 32 == 0 && P.K % 64 == 0 && P.K > 0 && P.lda % 2 == 0 &&
                P.ldb % 2 == 0 && aligned16(P.A) && aligned16(P.B)) {
         constexpr int W = WS_DMA_WAVES, ST = WS_DMA_STAGES, SK = WS_DMA_SK;
-        const bool c2 = fold_chunks((int64_t)P.p, false, P.K, W, SK) != 0;
+        const bool c2 = dma_centre((int64_t)P.p, P.K, 32, W, SK);
         P.kc_tiles = fold_chunks((int64_t)P.p, c2, P.K, W, SK);
         P.tiles_m = (int32_t)(P.M / 32);
         P.tiles_n = (int32_t)(P.N / 32);
         const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(64 * W);
-        if (c2) ws_launch((gemm_dma_kernel<T, true, W, ST, SK>), grid, block, 0, s, P);
-        else ws_launch((gemm_dma_kernel<T, false, W, ST, SK>), grid, block, 0, s, P);
+        if (c2) ws_launch((gemm_dma_kernel<T, true, 32, W, ST, SK>), grid, block, 0, s, P);
+        else ws_launch((gemm_dma_kernel<T, false, 32, W, ST, SK>), grid, block, 0, s, P);
     } else {
         P.tiles_m = (int32_t)((P.M + 31) / 32);
         P.tiles_n = (int32_t)((P.N + 31) / 32);

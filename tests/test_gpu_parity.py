@@ -54,13 +54,15 @@ def test_extreme_entries_long_k():
     assert np.all(C2 == k % p)
 
 
-# Whole 32 x 32 tiles and 64-deep inner chunks with aligned rows: the
-# pipelined small-product kernel, both storage types, folds included.
+# Whole 32 x 32 or 64 x 64 tiles and 64-deep inner chunks with aligned rows:
+# the pipelined kernels, both storage types, folds included.
 @pytest.mark.parametrize("dtype", [capi.WS_F64, capi.WS_I64])
 @pytest.mark.parametrize("shape,p", [((32, 64, 32), 65521), ((96, 640, 160), 8388593),
                                      ((128, 128, 128), 1048573), ((256, 4096, 256), 8388593),
                                      ((64, 2048, 64), 16777213), ((512, 512, 512), 65521),
-                                     ((32, 8192, 64), 16777213)])
+                                     ((32, 8192, 64), 16777213), ((1024, 1024, 1024), 65521),
+                                     ((1024, 512, 1024), 8388593), ((2048, 128, 512), 1048573),
+                                     ((1024, 2048, 512), 16777213)])
 def test_whole_tile_products(shape, p, dtype):
     m, k, n = shape
     print("whole-tile", shape, p, dtype, flush=True)
@@ -71,11 +73,27 @@ def test_whole_tile_products(shape, p, dtype):
         assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, alpha, beta, p)), (alpha, beta)
 
 
-def test_whole_tile_largest_centred_sums():
+@pytest.mark.parametrize("shape", [(256, 4096, 256), (1024, 2048, 1024)])
+def test_whole_tile_largest_uncentred_sums(shape):
+    """All entries p-1 for p = 8388593, where the pipelined kernels keep the
+    operands uncentred and fold the accumulators instead: each fold period
+    brings a partial sum within a few p of 2^53."""
+    p = 8388593
+    m, k, n = shape
+    A = np.full((m, k), p - 1, dtype=np.int64)
+    B = np.full((k, n), p - 1, dtype=np.int64)
+    st, C2, _, _ = call(capi.WS_CLASSICAL, A, B, None, 1, 0, p, 0)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    assert np.all(C2 == k % p)
+
+
+@pytest.mark.parametrize("shape", [(64, 8192, 96), (1024, 2048, 1024)])
+def test_whole_tile_largest_centred_sums(shape):
     """Centred operands of the largest magnitude, (p-1)/2 against -(p-1)/2,
-    over 8192 inner indices: every partial sum needs the periodic folds."""
+    over long inner dimensions: every partial sum needs the periodic folds
+    (32 x 32 and 64 x 64 tiles)."""
     p = 16777213
-    m, k, n = 64, 8192, 96
+    m, k, n = shape
     A = np.full((m, k), (p - 1) // 2, dtype=np.int64)
     B = np.full((k, n), (p + 1) // 2, dtype=np.int64)
     st, C2, _, _ = call(capi.WS_CLASSICAL, A, B, None, 1, 0, p, 0)
