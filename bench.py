@@ -1,16 +1,29 @@
 """Benchmark: exact Winograd products over Z/pZ on one MI355X.
 
-Default workload: C <- A*B + C mod 65521 with m = k = n = 4096, three
-Winograd levels under the read-only two-temporary accumulating schedule
-(Table 9), binary64 matrix-core base case.  One step is one such product on
-inputs already resident in HBM.  The same workload is also timed under the
-input-overwriting accumulating schedule (Table 6; A and B are restored from
-pristine copies outside the timed window) and as one classical product.
+Default workload (acc_4096_p65521_l3): C <- A*B + C mod 65521 with m = k = n =
+4096, three Winograd levels under the read-only two-temporary accumulating
+schedule (Table 9), binary64 matrix-core base case.  One step is one such
+product on inputs already resident in HBM.  The same workload is also timed
+under the input-overwriting accumulating schedule (Table 6; A and B are
+restored from pristine copies outside the timed window) and as one classical
+product.
+
+--workload selects one of the other configurations instead:
+  t1_512_p65521_l1_i64          C = A*B mod 65521, 512^3, int64 storage, Table 1, one level
+  ipmm_8192x4096x8192_p8388593  C = A*B mod 8388593, Algorithm 2 (read-only, in place),
+                                one level, against Table 1 and classical
+  t1_16384_p1048573             C = A*B mod 1048573, 16384^3, schedule, depth and base
+                                chosen by the autotuner, against the binary64 and 8-bit
+                                digit bases under fixed schedules
+  batch_2000                    2000 products, sizes log-uniform in [64, 2048], moduli
+                                from {65521, 1048573, 8388593}, autotuned, one hipGraph
+                                replay of the persistent batched launches
 
 Prints one JSON line on stdout.  Extra fields: the peak temporary bytes of
 each schedule, the comparator rates, a roofline entry for the dominant kernel
-class (time from events on the launch stream), and the oracle's rate on a
-bounded sample of the same product on the host cores.
+class (time from start/stop events that the kernel dispatches stamp on the
+launch stream) and the oracle's rate on a bounded sample of the same work on
+the host cores.
 """
 import argparse
 import json
@@ -24,7 +37,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_F64_MFMA_TFLOPS = 78.6
+PEAK_I8_MFMA_TOPS = 5000.0
 PEAK_HBM_GBS = 8000.0
+METRIC = "mod-p matmul effective Gop/s (2mnk/s) + peak temp bytes vs classical mod-p GEMM"
+SCHEDULE_NAMES = {0: "classical", 1: "two temporaries (Table 1 / Table 9)",
+                  2: "input-overwriting (Table 3 / Table 6)",
+                  3: "read-only in place (Algorithm 2)", 4: "three temporaries (Table 2)",
+                  6: "overwrite, accumulate right (Table 5)", 7: "accumulate right (Table 7)"}
+WORKLOADS = ("acc_4096_p65521_l3", "t1_512_p65521_l1_i64", "ipmm_8192x4096x8192_p8388593",
+             "t1_16384_p1048573", "batch_2000")
 
 
 def log(msg):
@@ -40,11 +61,12 @@ def kernels_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(gemm_dominant):
+def measured_traffic(workload, gemm_dominant):
     """HBM bytes per launch of the dominant kernel, from the FETCH_SIZE and
     WRITE_SIZE counter runs recorded in profiles/ (scaled by the plain-copy
-    calibration there); None when the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", "traffic_acc_4096_p65521_l3.json")
+    calibration there); None when there is no record for the workload or the
+    kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -54,12 +76,327 @@ def measured_traffic(gemm_dominant):
     return rec.get(key, {}).get("bytes_per_launch")
 
 
+class Ctx:
+    """Device, stream and timing helpers shared by the workloads."""
+
+    def __init__(self, args):
+        import torch
+        from paper_0707_2347_amd import capi, inputs
+        self.torch, self.capi, self.inputs, self.args = torch, capi, inputs, args
+        self.dev = torch.device("cuda:0")
+        self.stream = torch.cuda.current_stream()
+
+    def to_dev(self, x, dtype=None):
+        t = self.torch.from_numpy(x)
+        return t.to(self.dev) if dtype is None else t.to(self.dev).to(dtype)
+
+    def timed(self, fn, steps, warmup):
+        """Wall time per call of fn over `steps` calls after `warmup` calls,
+        bracketed by device synchronisation."""
+        for _ in range(warmup):
+            fn()
+        self.torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        self.torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    def event_ms(self, fn, reps, before=None):
+        """Average event-timed duration of fn on the current stream."""
+        torch = self.torch
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        tot = 0.0
+        for i in range(reps + 1):
+            if before:
+                before()
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if i > 0:
+                tot += e0.elapsed_time(e1)
+        return tot / reps
+
+    def traced(self, args, ntraced, int8_ops=False):
+        """Kernel-class times of `ntraced` traced calls -> roofline entry."""
+        capi = self.capi
+        capi.wsmul_reset_stats()
+        targs = capi.ws_args.from_buffer_copy(args)
+        targs.flags |= capi.WS_FLAG_TRACE
+        for _ in range(ntraced):
+            capi.check(capi.wsmul_mod_p_ex(targs))
+        tr = capi.wsmul_get_trace()
+        gemm_avg_ms = tr.gemm_ms / max(tr.gemm_launches, 1)
+        add_avg_ms = tr.add_ms / max(tr.add_launches, 1)
+        gemm_flops_per = tr.gemm_flops / max(tr.gemm_launches, 1)
+        add_bytes_per = tr.add_bytes / max(tr.add_launches, 1)
+        log("trace: base products %d x %.4f ms, additions %d x %.4f ms"
+            % (tr.gemm_launches, gemm_avg_ms, tr.add_launches, add_avg_ms))
+        per_step = {"base_products": round(tr.gemm_ms / ntraced, 4),
+                    "additions": round(tr.add_ms / ntraced, 4)}
+        gemm_dominant = tr.gemm_ms >= tr.add_ms
+        traffic = measured_traffic(self.args.workload, gemm_dominant)
+        if gemm_dominant and tr.gemm_launches:
+            if int8_ops:
+                # 9 digit products of 2*M*N*K int8 ops each per base product
+                ops = 9.0 * gemm_flops_per
+                ach = ops / (gemm_avg_ms * 1e-3) / 1e12
+                roof = {"bound": "mfma", "kernel": "base product (int8 16x16x64 matrix cores, "
+                        "3 x 3 digit products, digit split included)",
+                        "achieved": round(ach, 2), "peak": PEAK_I8_MFMA_TOPS, "unit": "TOP/s",
+                        "frac": round(ach / PEAK_I8_MFMA_TOPS, 4), "traffic": traffic,
+                        "avg_launch_ms": round(gemm_avg_ms, 5), "int8_ops_per_launch": ops}
+            else:
+                ach = gemm_flops_per / (gemm_avg_ms * 1e-3) / 1e12
+                roof = {"bound": "mfma", "kernel": "base product (f64 16x16x4 matrix cores)",
+                        "achieved": round(ach, 3), "peak": PEAK_F64_MFMA_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(ach / PEAK_F64_MFMA_TFLOPS, 4),
+                        "traffic": traffic, "avg_launch_ms": round(gemm_avg_ms, 5),
+                        "flops_per_launch": gemm_flops_per}
+        else:
+            gbs = add_bytes_per / (add_avg_ms * 1e-3) / 1e9
+            roof = {"bound": "hbm", "kernel": "fused addition rows", "achieved": round(gbs, 1),
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                    "traffic": traffic, "avg_launch_ms": round(add_avg_ms, 5),
+                    "bytes_per_launch": add_bytes_per}
+        counts = {"base_products": int(tr.gemm_launches // ntraced),
+                  "addition_groups": int(tr.add_launches // ntraced)}
+        return roof, per_step, counts
+
+
+def cpu_baseline_rows(A, B, C, alpha, beta, p, budget_s=12.0):
+    """The oracle on the first rows of the same product (the whole product if
+    it fits the budget), timed on the host cores."""
+    from oracle import ref
+    threads = ref.threads_available()
+    m, k = A.shape
+    n = B.shape[1]
+    Ai, Bi = A.astype(np.int64, copy=False), B.astype(np.int64, copy=False)
+    Ci = None if C is None else C.astype(np.int64, copy=False)
+    rows = min(m, 16)
+    t_s = time.perf_counter()
+    ref.matmul_mod_p(Ai[:rows], Bi, None if Ci is None else Ci[:rows], alpha, beta, p,
+                     threads=threads)
+    dt = max(time.perf_counter() - t_s, 1e-4)
+    rows = int(min(m, max(16, rows * budget_s / dt)))
+    reps = 1 if rows < m else max(1, int(budget_s / max(dt * m / 16.0, 1e-3)))
+    log("cpu baseline: oracle on %d rows x %d x %d, %d threads, %d run(s)"
+        % (rows, k, n, threads, reps))
+    t_s = time.perf_counter()
+    for _ in range(reps):
+        ref.matmul_mod_p(Ai[:rows], Bi, None if Ci is None else Ci[:rows], alpha, beta, p,
+                         threads=threads)
+    dt = (time.perf_counter() - t_s) / reps
+    return {"value": round(2.0 * rows * k * n / dt / 1e9, 3), "unit": "Gop/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "rows 0..%d of the same product (%d x %d x %d), %d run(s) of %.1f s"
+                      % (rows - 1, rows, k, n, reps, dt)}
+
+
+def line(ctx, value, ms_step, dtype, config, roofline, cpu, extra):
+    a = ctx.args
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "Gop/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(ms_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic", "config": config, "roofline": roofline, "cpu_baseline": cpu}
+    out.update(extra)
+    return out
+
+
+# ---------------------------------------------------------------- workloads
+def single_product(ctx, name):
+    """The four single-product workloads."""
+    capi, inputs, torch = ctx.capi, ctx.inputs, ctx.torch
+    a = ctx.args
+    w = inputs.WORKLOADS[name]
+    m, k, n, p = w["m"], w["k"], w["n"], w["p"]
+    alpha, beta = w["alpha"], w["beta"]
+    i64 = w["dtype"] == "i64"
+    dt = capi.WS_I64 if i64 else capi.WS_F64
+    log("generating inputs %dx%dx%d p=%d" % (m, k, n, p))
+    if i64:
+        A, B, C = inputs.uniform(w["seed"], m, k, n, p, with_c=beta != 0)
+    else:
+        A, B, C = inputs.uniform_f64(w["seed"], m, k, n, p, with_c=beta != 0)
+    dA, dB = ctx.to_dev(A), ctx.to_dev(B)
+    dC = ctx.to_dev(C) if C is not None else torch.zeros((m, n), dtype=dA.dtype, device=ctx.dev)
+    flops = 2.0 * m * n * k
+
+    def mkargs(schedule, levels, base=capi.WS_BASE_F64_MFMA, ws=None, nbytes=0):
+        return capi.make_args(m, k, n, p, dA, dB, dC, alpha, beta, schedule, levels, dtype=dt,
+                              base=base, stream=ctx.stream, workspace=ws, workspace_bytes=nbytes)
+
+    def ws_for(schedule, levels):
+        nbytes = capi.wsmul_workspace_bytes(m, k, n, dt, schedule, levels, int(beta != 0))
+        return torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=ctx.dev), nbytes
+
+    def run(args):
+        capi.check(capi.wsmul_mod_p_ex(args))
+
+    extra = {}
+    int8 = False
+    if name == "acc_4096_p65521_l3":
+        sched, lev, base, label = capi.WS_TWO_TEMP, a.levels, capi.WS_BASE_F64_MFMA, \
+            "table9-accumulate-two-temporaries"
+        config = {"workload": name, "m": m, "k": k, "n": n, "p": p, "op": "C <- A*B + C",
+                  "schedule": label, "levels": lev, "base": "f64 matrix cores",
+                  "parallelism": "single GPU"}
+    elif name == "t1_512_p65521_l1_i64":
+        sched, lev, base = capi.WS_TWO_TEMP, 1, capi.WS_BASE_F64_MFMA
+        config = {"workload": name, "m": m, "k": k, "n": n, "p": p, "op": "C = A*B",
+                  "schedule": "table1-two-temporaries", "levels": lev,
+                  "base": "f64 matrix cores", "storage": "int64", "parallelism": "single GPU"}
+    elif name == "ipmm_8192x4096x8192_p8388593":
+        sched, lev, base = capi.WS_READONLY_INPLACE, 1, capi.WS_BASE_F64_MFMA
+        config = {"workload": name, "m": m, "k": k, "n": n, "p": p, "op": "C = A*B",
+                  "schedule": "algorithm2-readonly-inplace", "levels": lev,
+                  "base": "f64 matrix cores", "parallelism": "single GPU"}
+    else:   # t1_16384_p1048573: the autotuner decides
+        st, sched, lev, base = capi.wsmul_autotune(m, k, n, p, dt, 2 ** 62, capi.WS_AUTO, -1,
+                                                   capi.WS_BASE_AUTO, beta)
+        capi.check(st)
+        int8 = base == capi.WS_BASE_I8_LIMBS
+        config = {"workload": name, "m": m, "k": k, "n": n, "p": p, "op": "C = A*B",
+                  "schedule": "autotuned: " + SCHEDULE_NAMES.get(sched, str(sched)),
+                  "levels": lev,
+                  "base": "int8 digits (3 balanced base-256 digits)" if int8
+                  else "f64 matrix cores", "parallelism": "single GPU"}
+
+    ws, nbytes = ws_for(sched, lev)
+    head = mkargs(sched, lev, base, ws, nbytes)
+    steps, warmup = a.steps, a.warmup
+    log("timing %d steps (%s, %d levels)" % (steps, config["schedule"], lev))
+    ms_step = ctx.timed(lambda: run(head), steps, warmup)
+    stats = capi.wsmul_get_stats()
+    value = flops / (ms_step * 1e-3) / 1e9
+    log("%s: %.3f ms/step, %.1f Gop/s, temporaries %d B" % (name, ms_step, value,
+                                                           stats.workspace_bytes))
+    roof, per_step, counts = ctx.traced(head, max(1, min(steps, 5)), int8_ops=int8)
+    extra["peak_temp_bytes"] = int(stats.workspace_bytes)
+    extra["launches_per_step"] = counts
+    extra["kernel_time_per_step_ms"] = per_step
+    del ws
+
+    if not a.no_compare:
+        reps = max(3, steps // 2)
+
+        def compare(key, schedule, levels, base=capi.WS_BASE_F64_MFMA, restore=False):
+            w2, nb2 = ws_for(schedule, levels) if schedule != capi.WS_CLASSICAL else (None, 0)
+            args2 = mkargs(schedule, levels, base, w2, nb2)
+            run(args2)
+            torch.cuda.synchronize()
+            before = None
+            if restore:
+                A0, B0 = dA.clone(), dB.clone()
+
+                def before():
+                    dA.copy_(A0)
+                    dB.copy_(B0)
+            ms = ctx.event_ms(lambda: run(args2), reps, before)
+            extra[key] = {"ms_per_step": round(ms, 4),
+                          "gops": round(flops / (ms * 1e-3) / 1e9, 2),
+                          "peak_temp_bytes": int(nb2)}
+            log("%s: %.3f ms, %.1f Gop/s" % (key, ms, flops / (ms * 1e-3) / 1e9))
+            return ms
+
+        cl_ms = compare("classical", capi.WS_CLASSICAL, 0)
+        if name == "acc_4096_p65521_l3":
+            compare("overwrite_table6", capi.WS_OVERWRITE, lev, restore=True)
+        elif name == "ipmm_8192x4096x8192_p8388593":
+            compare("two_temporaries_table1", capi.WS_TWO_TEMP, 1)
+        elif name == "t1_16384_p1048573":
+            compare("classical_int8_digits", capi.WS_CLASSICAL, 0, capi.WS_BASE_I8_LIMBS)
+            compare("table1_1_level_int8_digits", capi.WS_TWO_TEMP, 1, capi.WS_BASE_I8_LIMBS)
+            compare("table1_2_levels_f64", capi.WS_TWO_TEMP, 2)
+        extra["speedup_vs_classical"] = round(cl_ms / ms_step, 4)
+
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline_rows(A, B, C, alpha, beta, p)
+    return line(ctx, value, ms_step, "int64" if i64 else "f64", config, roof, cpu, extra)
+
+
+def batch_2000(ctx):
+    """2000 autotuned products in one captured graph; one step is one replay."""
+    capi, inputs, torch = ctx.capi, ctx.inputs, ctx.torch
+    a = ctx.args
+    probs = inputs.batch_problems()
+    log("generating %d batch products" % len(probs))
+    args, keep, host = [], [], []
+    flops = 0.0
+    for pr in probs:
+        m, k, n, p = pr["m"], pr["k"], pr["n"], pr["p"]
+        A, B = inputs.batch_inputs(pr)
+        dA, dB = ctx.to_dev(A), ctx.to_dev(B)
+        dC = torch.empty((m, n), dtype=torch.float64, device=ctx.dev)
+        keep.append((dA, dB, dC))
+        if len(host) < 200:   # the CPU baseline samples the first products only
+            host.append((A, B, p))
+        flops += 2.0 * m * n * k
+        args.append(capi.make_args(m, k, n, p, dA, dB, dC, 1, 0, capi.WS_AUTO, -1,
+                                   base=capi.WS_BASE_F64_MFMA, stream=ctx.stream))
+    st, handle = capi.wsmul_graph_capture(args)
+    capi.check(st)
+    stats = capi.wsmul_get_stats()
+    phases = capi.wsmul_get_stats().batch_phases
+    try:
+        def replay():
+            capi.check(capi.wsmul_graph_launch(handle, ctx.stream))
+        log("timing %d graph replays" % a.steps)
+        ms_step = ctx.timed(replay, a.steps, a.warmup)
+        value = flops / (ms_step * 1e-3) / 1e9
+        log("batch: %.3f ms/replay, %.1f Gop/s" % (ms_step, value))
+        ach = flops / (ms_step * 1e-3) / 1e12
+        roof = {"bound": "mfma", "kernel": "batch_kernel (persistent; one launch per phase, "
+                "%d phases, phase 0 holds every classical product)" % phases,
+                "achieved": round(ach, 3), "peak": PEAK_F64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_F64_MFMA_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": None, "flops_per_replay": flops}
+        extra = {"peak_temp_bytes": int(stats.workspace_bytes),
+                 "device_block_bytes": int(stats.internal_alloc_bytes), "phases": int(phases)}
+        if not a.no_compare:
+            def separate():
+                for x in args:
+                    capi.check(capi.wsmul_mod_p_ex(x))
+            ms2 = ctx.event_ms(separate, 2)
+            extra["separate_calls"] = {"ms_per_step": round(ms2, 3),
+                                       "gops": round(flops / (ms2 * 1e-3) / 1e9, 2)}
+            log("separate calls: %.3f ms" % ms2)
+    finally:
+        capi.wsmul_graph_destroy(handle)
+    cpu = None
+    if not a.no_cpu:
+        from oracle import ref
+        threads = ref.threads_available()
+        t_s = time.perf_counter()
+        done, fl = 0, 0.0
+        for A, B, p in host:
+            ref.matmul_mod_p(A.astype(np.int64), B.astype(np.int64), None, 1, 0, p,
+                             threads=threads)
+            done += 1
+            fl += 2.0 * A.shape[0] * A.shape[1] * B.shape[1]
+            if time.perf_counter() - t_s > 12.0:
+                break
+        dt = time.perf_counter() - t_s
+        cpu = {"value": round(fl / dt / 1e9, 3), "unit": "Gop/s", "cores": threads,
+               "kind": "oracle", "sample": "the first %d of the 2000 products, %.1f s"
+                                           % (done, dt)}
+    config = {"workload": "batch_2000", "products": len(probs), "sizes": "m, k, n log-uniform "
+              "in [64, 2048]", "moduli": list(inputs.PRIMES), "op": "C = A*B",
+              "schedule": "autotuned per product", "base": "f64 matrix cores",
+              "launch": "hipGraph of persistent batched launches", "parallelism": "single GPU"}
+    return line(ctx, value, ms_step, "f64", config, roof, cpu, extra)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--levels", type=int, default=3)
+    ap.add_argument("--levels", type=int, default=3,
+                    help="Winograd levels of the default workload")
+    ap.add_argument("--workload", default=WORKLOADS[0], choices=WORKLOADS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparator schedules")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -73,8 +410,6 @@ def main():
 
     import torch
 
-    from paper_0707_2347_amd import capi, inputs
-
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda:0")
@@ -85,157 +420,11 @@ def main():
         print(json.dumps({"copy_probe_bytes": n * 8, "copies": 5}))
         return
 
-    w = inputs.WORKLOADS["acc_4096_p65521_l3"]
-    m, k, n, p = w["m"], w["k"], w["n"], w["p"]
-    L = args.levels
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
-    log("generating inputs %dx%dx%d p=%d" % (m, k, n, p))
-    A, B, C = inputs.uniform_f64(w["seed"], m, k, n, p, with_c=True)
-    dA = torch.from_numpy(A).to(dev)
-    dB = torch.from_numpy(B).to(dev)
-    dC = torch.from_numpy(C).to(dev)
-    A0, B0 = dA.clone(), dB.clone()
-
-    def ws_for(schedule):
-        nbytes = capi.wsmul_workspace_bytes(m, k, n, capi.WS_F64, schedule, L, 1)
-        buf = torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=dev)
-        return buf, nbytes
-
-    def mkargs(schedule, ws, nbytes, flags=0):
-        return capi.make_args(m, k, n, p, dA, dB, dC, 1, 1, schedule, L, stream=stream,
-                              workspace=ws, workspace_bytes=nbytes, flags=flags)
-
-    flops = 2.0 * m * n * k
-
-    # ---------------------------------------------------- headline: Table 9
-    ws, nbytes = ws_for(capi.WS_TWO_TEMP)
-    a_acc = mkargs(capi.WS_TWO_TEMP, ws, nbytes)
-    for _ in range(args.warmup):
-        capi.check(capi.wsmul_mod_p_ex(a_acc))
-    torch.cuda.synchronize()
-    log("timing %d steps (table 9, %d levels)" % (args.steps, L))
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        capi.check(capi.wsmul_mod_p_ex(a_acc))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    stats = capi.wsmul_get_stats()
-    value = flops / (ms_step * 1e-3) / 1e9
-    log("table 9: %.3f ms/step, %.1f Gop/s, temporaries %d B" % (ms_step, value,
-                                                                  stats.workspace_bytes))
-
-    # kernel-class times from events on the launch stream (separate traced steps)
-    capi.wsmul_reset_stats()
-    traced = mkargs(capi.WS_TWO_TEMP, ws, nbytes, flags=capi.WS_FLAG_TRACE)
-    ntraced = max(1, min(args.steps, 5))
-    for _ in range(ntraced):
-        capi.check(capi.wsmul_mod_p_ex(traced))
-    tr = capi.wsmul_get_trace()
-    gemm_avg_ms = tr.gemm_ms / max(tr.gemm_launches, 1)
-    add_avg_ms = tr.add_ms / max(tr.add_launches, 1)
-    gemm_flops_per = tr.gemm_flops / max(tr.gemm_launches, 1)
-    add_bytes_per = tr.add_bytes / max(tr.add_launches, 1)
-    gemm_tfs = gemm_flops_per / (gemm_avg_ms * 1e-3) / 1e12
-    add_gbs = add_bytes_per / (add_avg_ms * 1e-3) / 1e9
-    log("trace: base products %d x %.4f ms (%.2f TFLOP/s), additions %d x %.4f ms (%.0f GB/s)"
-        % (tr.gemm_launches, gemm_avg_ms, gemm_tfs, tr.add_launches, add_avg_ms, add_gbs))
-    traffic = measured_traffic(tr.gemm_ms >= tr.add_ms)
-    if tr.gemm_ms >= tr.add_ms:
-        roofline = {"bound": "mfma", "kernel": "base product (f64 16x16x4 matrix cores)",
-                    "achieved": round(gemm_tfs, 3), "peak": PEAK_F64_MFMA_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(gemm_tfs / PEAK_F64_MFMA_TFLOPS, 4),
-                    "traffic": traffic, "avg_launch_ms": round(gemm_avg_ms, 5),
-                    "flops_per_launch": gemm_flops_per}
+    ctx = Ctx(args)
+    if args.workload == "batch_2000":
+        out = batch_2000(ctx)
     else:
-        roofline = {"bound": "hbm", "kernel": "fused addition rows",
-                    "achieved": round(add_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(add_gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
-                    "avg_launch_ms": round(add_avg_ms, 5), "bytes_per_launch": add_bytes_per}
-    del ws
-
-    extra = {"peak_temp_bytes": int(stats.workspace_bytes),
-             "launches_per_step": {"base_products": int(stats.gemm_launches),
-                                   "addition_groups": int(stats.add_launches)},
-             "kernel_time_per_step_ms": {"base_products": round(tr.gemm_ms / ntraced, 4),
-                                         "additions": round(tr.add_ms / ntraced, 4)}}
-
-    # ---------------------------------------------------- comparators
-    if not args.no_compare:
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        # classical: one base product over the whole shape
-        a_cl = mkargs(capi.WS_CLASSICAL, None, 0)
-        capi.check(capi.wsmul_mod_p_ex(a_cl))
-        torch.cuda.synchronize()
-        reps = max(3, args.steps // 2)
-        ev0.record()
-        for _ in range(reps):
-            capi.check(capi.wsmul_mod_p_ex(a_cl))
-        ev1.record()
-        torch.cuda.synchronize()
-        cl_ms = ev0.elapsed_time(ev1) / reps
-        extra["classical"] = {"ms_per_step": round(cl_ms, 4),
-                              "gops": round(flops / (cl_ms * 1e-3) / 1e9, 2),
-                              "peak_temp_bytes": 0}
-        log("classical: %.3f ms, %.1f Gop/s" % (cl_ms, flops / (cl_ms * 1e-3) / 1e9))
-        # Table 6 (overwrites A and B): restore the inputs outside the window
-        ws6, nb6 = ws_for(capi.WS_OVERWRITE)
-        a_ov = mkargs(capi.WS_OVERWRITE, ws6, nb6)
-        tot = 0.0
-        for i in range(reps + 1):
-            dA.copy_(A0)
-            dB.copy_(B0)
-            ev0.record()
-            capi.check(capi.wsmul_mod_p_ex(a_ov))
-            ev1.record()
-            torch.cuda.synchronize()
-            if i > 0:
-                tot += ev0.elapsed_time(ev1)
-        ov_ms = tot / reps
-        extra["overwrite_table6"] = {"ms_per_step": round(ov_ms, 4),
-                                     "gops": round(flops / (ov_ms * 1e-3) / 1e9, 2),
-                                     "peak_temp_bytes": int(nb6)}
-        extra["speedup_vs_classical"] = round(cl_ms / ms_step, 4)
-        log("table 6: %.3f ms, %.1f Gop/s" % (ov_ms, flops / (ov_ms * 1e-3) / 1e9))
-        del ws6
-
-    # ---------------------------------------------------- CPU baseline
-    cpu = None
-    if not args.no_cpu:
-        from oracle import ref
-        threads = ref.threads_available()
-        Ai = A.astype(np.int64)
-        Bi = B.astype(np.int64)
-        Ci = C.astype(np.int64)
-        rows = 16
-        t_s = time.perf_counter()
-        ref.matmul_mod_p(Ai[:rows], Bi, Ci[:rows], 1, 1, p, threads=threads)
-        dt = time.perf_counter() - t_s
-        rows = int(min(m, max(16, rows * 12.0 / max(dt, 1e-3))))
-        reps = 1 if rows < m else max(1, int(10.0 / max(dt * m / 16.0, 1e-3)))
-        log("cpu baseline: oracle on %d rows x %d x %d, %d threads, %d run(s)"
-            % (rows, k, n, threads, reps))
-        t_s = time.perf_counter()
-        for _ in range(reps):
-            ref.matmul_mod_p(Ai[:rows], Bi, Ci[:rows], 1, 1, p, threads=threads)
-        dt = (time.perf_counter() - t_s) / reps
-        cpu = {"value": round(2.0 * rows * k * n / dt / 1e9, 3), "unit": "Gop/s",
-               "cores": threads, "kind": "oracle",
-               "sample": "rows 0..%d of the same product (%d x %d x %d), %d run(s) of %.1f s"
-                         % (rows - 1, rows, k, n, reps, dt)}
-
-    out = {"metric": "mod-p matmul effective Gop/s (2mnk/s) + peak temp bytes vs classical "
-                     "mod-p GEMM",
-           "value": round(value, 3), "unit": "Gop/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "acc_4096_p65521_l3", "m": m, "k": k, "n": n, "p": p,
-                      "op": "C <- A*B + C", "schedule": "table9-accumulate-two-temporaries",
-                      "levels": L, "base": "f64 matrix cores", "parallelism": "single GPU"},
-           "roofline": roofline, "cpu_baseline": cpu}
-    out.update(extra)
+        out = single_product(ctx, args.workload)
     print(json.dumps(out), flush=True)
 
 
