@@ -98,6 +98,16 @@ void fill_records(Batch &b, void *ws_base) {
             for (int t = 0; t < op.ntiles; ++t)
                 b.tasks.push_back(make_int2(o, t));
         }
+        // Longest tasks first: the persistent grid deals tasks round-robin,
+        // so every workgroup then gets one task from each cost band and the
+        // phase ends evenly.  A product tile costs its inner dimension (plus
+        // a fixed part); an addition chunk a fixed amount.
+        auto cost = [&](const int2 &t) {
+            const BatchOp &op = b.ops[t.x];
+            return op.kind == WS_OP_GEMM ? op.g.K + 64 : (int64_t)32;
+        };
+        std::stable_sort(b.tasks.begin() + (std::ptrdiff_t)b.phase_task.back(), b.tasks.end(),
+                         [&](const int2 &x, const int2 &y) { return cost(x) > cost(y); });
         b.phase_task.push_back(b.tasks.size());
     }
 }
