@@ -3,9 +3,10 @@
 // Every admissible candidate is expanded into its real fused plan (the plan
 // cache keeps this cheap) and costed operation by operation with rates
 // measured on MI355X for the kernels of this library:
-//   base products, binary64 matrix cores: 58 TFLOP/s for the 128 x 128 tile
-//     class (x0.87 when the accumulators must be folded), 30 TFLOP/s for the
-//     64 x 64 class, 19 TFLOP/s for the split-K class, 8 us floor per launch;
+//   base products, binary64 matrix cores: 60 TFLOP/s (57 when folding) for
+//     whole 128 x 128 tiles, 58 (50) for ragged large products, 45 / 30
+//     TFLOP/s for the 64 x 64 class with whole / ragged tiles, 25 / 19 for
+//     the small class, 7 us floor per launch;
 //   base products, 8-bit digits: 300 / 265 / 180 / 120 / 40 TFLOP/s
 //     (equivalent) by 128 x 128 tile count, plus the digit split passes
 //     (bytes at 5 TB/s);
@@ -30,11 +31,18 @@ double gemm_f64_us(int64_t M, int64_t N, int64_t K, int64_t p) {
     const double flops = 2.0 * (double)M * (double)N * (double)K;
     const int64_t big = ((M + 127) / 128) * ((N + 127) / 128);
     const int64_t mid = ((M + 63) / 64) * ((N + 63) / 64);
-    double rate = big >= 512 ? 58e12 : (mid >= 256 ? 30e12 : 19e12);
     const double per_tile = 16.0 * (double)(p - 1) * (double)(p - 1);
-    if (per_tile * ((double)K / 16.0 + 1.0) >= 9.0e15)
-        rate *= 0.87;   // accumulators folded back to residues during the loop
-    return std::max(8.0, flops / rate * 1e6);
+    const bool folds = per_tile * ((double)K / 16.0 + 1.0) >= 9.0e15;
+    double rate;
+    if (big >= 256 && M % 128 == 0 && N % 128 == 0 && K % 16 == 0)
+        rate = folds ? 57e12 : 60e12;             // pipelined 128 x 128 tiles
+    else if (big >= 512)
+        rate = folds ? 50e12 : 58e12;             // LDS-staged 128 x 128 tiles, centred when folding
+    else if (mid >= 256)
+        rate = (M % 64 == 0 && N % 64 == 0 && K % 64 == 0) ? 45e12 : 30e12;
+    else
+        rate = (M % 32 == 0 && N % 32 == 0 && K % 64 == 0) ? 25e12 : 19e12;
+    return std::max(7.0, flops / rate * 1e6);
 }
 
 double gemm_digits_us(int64_t M, int64_t N, int64_t K) {

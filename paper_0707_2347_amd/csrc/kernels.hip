@@ -739,6 +739,147 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
     }
 }
 
+// Large base products of whole 128 x 128 tiles and 16-deep K-steps with
+// 16-byte aligned rows: one 128 x 128 output tile per workgroup, eight waves
+// in a 2 x 4 grid of 64 x 32 wave tiles (two waves per SIMD), K-steps of 16 in
+// four LDS buffers filled by direct global-to-LDS loads three steps ahead, one
+// workgroup barrier per K-step (the buffers are shared by the waves).  The
+// finished tile is staged through the buffers so that the fused epilogue runs
+// on whole rows.  A-rows of 128 bytes and B-rows of 1 KB are piece-swizzled as
+// in gemm_dma_kernel.
+#ifndef WS_BIG_ENABLE
+#define WS_BIG_ENABLE 1
+#endif
+namespace dmak {
+// This wave's loads of a K-step have landed (at most n of its loads, the
+// later K-steps', in flight), then every wave's; no fence, so the later loads
+// stay in flight across the barrier.
+__device__ __forceinline__ void wait_loads_barrier(int n) {
+    if (n >= 8) asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
+    else if (n >= 4) asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+}
+constexpr int BIG_TM = 128, BIG_SK = 16, BIG_STAGES = 4;
+constexpr int BIG_A_BYTES = BIG_TM * BIG_SK * 8, BIG_SUB_BYTES = 2 * BIG_A_BYTES;
+}  // namespace dmak
+
+template <typename T, bool CENTRE>
+__global__ __launch_bounds__(512) void gemm_big_kernel(GemmParams P) {
+    using namespace dmak;
+    constexpr int TM = BIG_TM, SK = BIG_SK, STAGES = BIG_STAGES, A_BYTES = BIG_A_BYTES,
+                  SUB_BYTES = BIG_SUB_BYTES;
+    static_assert(STAGES * SUB_BYTES >= TM * TM * 8, "the output tile fits the buffers");
+    __shared__ __attribute__((aligned(16))) char lds[BIG_STAGES * BIG_SUB_BYTES];
+    int32_t tm, tn;
+    tile_of(P.tiles_m, P.tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * TM, n0 = (int64_t)tn * TM;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;        // 2 x 4 waves of 64 x 32
+    const int li = lane & 15, kq = lane >> 4;
+    const char *A = static_cast<const char *>(P.A);
+    const char *B = static_cast<const char *>(P.B);
+    const int64_t nst = P.K / SK;
+
+    // Loads of K-step t: sixteen instructions of 8 A-rows (128 bytes each),
+    // sixteen of one B-row (1 KB each); four per wave.
+    auto issue = [&](int st, int64_t t) {
+        const int64_t k0 = t * SK;
+        char *base = lds + st * SUB_BYTES;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int q = wave + 8 * j;
+            if (j < 2) {
+                const int r = 8 * q + (lane >> 3), piece = (lane & 7) ^ aswz<16>(r);
+                __builtin_amdgcn_global_load_lds(A + ((m0 + r) * P.lda + k0) * 8 + piece * 16,
+                                                 base + q * 1024, 16, 0, 0);
+            } else {
+                const int k = q - 16, piece = lane ^ bswz<16>(k);
+                __builtin_amdgcn_global_load_lds(B + ((k0 + k) * P.ldb + n0) * 8 + piece * 16,
+                                                 base + A_BYTES + k * 1024, 16, 0, 0);
+            }
+        }
+    };
+    auto cvt = [&](T raw) {
+        const double x = to_f64(raw);
+        return (CENTRE && x > P.half) ? x - P.p : x;
+    };
+
+    f64x4 acc[4][2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    int since_fold = 0;
+
+#pragma unroll
+    for (int st = 0; st < STAGES - 1; ++st)
+        if (st < nst)
+            issue(st, st);
+    for (int64_t t = 0; t < nst; ++t) {
+        wait_loads_barrier(4 * (int)std::max<int64_t>(0, std::min<int64_t>(t + STAGES - 2, nst - 1) - t));
+        if (t + STAGES - 1 < nst)
+            issue((int)((t + STAGES - 1) % STAGES), t + STAGES - 1);
+        const char *sa = lds + (int)(t % STAGES) * SUB_BYTES;
+        const char *sb = sa + A_BYTES;
+        // lane (li, kq) holds inner indices 4*kq + s, s < 4
+        double a[4][4], b[2][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = wm * 64 + 16 * i + li;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const Pair<T> v = *reinterpret_cast<const Pair<T> *>(
+                    sa + r * (SK * 8) + ((2 * kq + h) ^ aswz<16>(r)) * 16);
+                a[i][2 * h] = cvt(v.x);
+                a[i][2 * h + 1] = cvt(v.y);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int k = 4 * kq + s, col = wn * 32 + 16 * j + li;
+                b[j][s] = cvt(*reinterpret_cast<const T *>(
+                    sb + k * (TM * 8) + ((col >> 1) ^ bswz<16>(k)) * 16 + (col & 1) * 8));
+            }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i][s], b[j][s], acc[i][j], 0, 0, 0);
+        if (P.kc_tiles > 0 && ++since_fold == P.kc_tiles) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[i][j][v] = mod_reduce(acc[i][j][v], P.p, P.pinv);
+            since_fold = 0;
+        }
+    }
+
+    // Stage the reduced products (alpha applied) and run the epilogue on
+    // whole rows.  Output of the 16 x 16 x 4 op: lane l, element v is row
+    // l/16 + 4v, column l%16.
+    __syncthreads();
+    double *stage = reinterpret_cast<double *>(lds);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                stage[(wm * 64 + 16 * i + kq + 4 * v) * TM + wn * 32 + 16 * j + li] =
+                    product_residue(P, acc[i][j][v]);
+    __syncthreads();
+    for (int e = tid; e < TM * TM; e += 512)
+        epilogue_apply<T>(P, stage[e], m0 + e / TM, n0 + e % TM);
+}
+
 // Fold period of gemm_dma_kernel in sub-chunks: each adds sk products of
 // magnitude at most m^2 to a wave's accumulators; 0 if a wave's whole share
 // of the inner dimension fits below 2^53.
@@ -785,7 +926,19 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
     const bool centre = fold_tiles((int64_t)P.p, false, P.K) != 0;
     P.kc_tiles = fold_tiles((int64_t)P.p, centre, P.K);
     P.half = std::floor(P.p / 2.0);
-    if (big >= 512) {
+    if (WS_BIG_ENABLE && big >= 256 && P.M % 128 == 0 && P.N % 128 == 0 && P.K % 16 == 0 &&
+        P.K > 0 && P.lda % 2 == 0 && P.ldb % 2 == 0 && aligned16(P.A) && aligned16(P.B)) {
+        // Centre only when uncentred folds (a reduction of 32 accumulators
+        // per lane) would cost more than centring 24 operands per K-step.
+        const int32_t t_nc = fold_chunks((int64_t)P.p, false, P.K, 1, 16);
+        const bool c2 = t_nc != 0 && 12.0 * 32.0 / (double)t_nc > 4.0 * 24.0;
+        P.kc_tiles = fold_chunks((int64_t)P.p, c2, P.K, 1, 16);
+        P.tiles_m = (int32_t)(P.M / 128);
+        P.tiles_n = (int32_t)(P.N / 128);
+        const dim3 grid((uint32_t)big), block(512);
+        if (c2) ws_launch((gemm_big_kernel<T, true>), grid, block, 0, s, P);
+        else ws_launch((gemm_big_kernel<T, false>), grid, block, 0, s, P);
+    } else if (big >= 512) {
         P.tiles_m = (int32_t)((P.M + 127) / 128);
         P.tiles_n = (int32_t)((P.N + 127) / 128);
         const dim3 grid((uint32_t)big), block(256);

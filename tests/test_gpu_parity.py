@@ -54,15 +54,16 @@ def test_extreme_entries_long_k():
     assert np.all(C2 == k % p)
 
 
-# Whole 32 x 32 or 64 x 64 tiles and 64-deep inner chunks with aligned rows:
-# the pipelined kernels, both storage types, folds included.
+# Whole 32 x 32, 64 x 64 or 128 x 128 tiles and 64-deep inner chunks with
+# aligned rows: the pipelined kernels, both storage types, folds included.
 @pytest.mark.parametrize("dtype", [capi.WS_F64, capi.WS_I64])
 @pytest.mark.parametrize("shape,p", [((32, 64, 32), 65521), ((96, 640, 160), 8388593),
                                      ((128, 128, 128), 1048573), ((256, 4096, 256), 8388593),
                                      ((64, 2048, 64), 16777213), ((512, 512, 512), 65521),
                                      ((32, 8192, 64), 16777213), ((1024, 1024, 1024), 65521),
                                      ((1024, 512, 1024), 8388593), ((2048, 128, 512), 1048573),
-                                     ((1024, 2048, 512), 16777213)])
+                                     ((1024, 2048, 512), 16777213), ((4096, 256, 2048), 8388593),
+                                     ((2048, 1024, 4096), 16777213), ((4096, 512, 2048), 65521)])
 def test_whole_tile_products(shape, p, dtype):
     m, k, n = shape
     print("whole-tile", shape, p, dtype, flush=True)
@@ -73,7 +74,7 @@ def test_whole_tile_products(shape, p, dtype):
         assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, alpha, beta, p)), (alpha, beta)
 
 
-@pytest.mark.parametrize("shape", [(256, 4096, 256), (1024, 2048, 1024)])
+@pytest.mark.parametrize("shape", [(256, 4096, 256), (1024, 2048, 1024), (4096, 1024, 2048)])
 def test_whole_tile_largest_uncentred_sums(shape):
     """All entries p-1 for p = 8388593, where the pipelined kernels keep the
     operands uncentred and fold the accumulators instead: each fold period
@@ -87,7 +88,7 @@ def test_whole_tile_largest_uncentred_sums(shape):
     assert np.all(C2 == k % p)
 
 
-@pytest.mark.parametrize("shape", [(64, 8192, 96), (1024, 2048, 1024)])
+@pytest.mark.parametrize("shape", [(64, 8192, 96), (1024, 2048, 1024), (2048, 1024, 4096)])
 def test_whole_tile_largest_centred_sums(shape):
     """Centred operands of the largest magnitude, (p-1)/2 against -(p-1)/2,
     over long inner dimensions: every partial sum needs the periodic folds
