@@ -44,6 +44,13 @@ Readings of the paper taken here (where it is silent or garbled):
 * At the base case an "overwriting" callee is a plain classical product and
   leaves its operands unchanged (so the final state of overwritten inputs is
   fully determined by the tables).
+* Section 7.2 (blocked accumulation) with a block count t: A, B and C are
+  cut along every dimension into t consecutive parts (the paper's n/t when t
+  divides the dimension; otherwise parts of ceil(d/t) rounded up to a multiple
+  of 2**L, the last one shorter).  Block C_ij accumulates the products
+  A_il B_lj for l = 1..t in order, the first with beta and the others with 1,
+  each by one call of the base schedule (Table 2, or Table 9 for square
+  blocks).  Only one call's temporaries exist at a time.
 * Algorithm 2 with the depth parameter L: at depth d < L the three quadrant
   products are Winograd calls of depth L - d, with inner dimension cut in
   chunks of K = min(s/2, k); at depth L the remaining corner is a classical
@@ -56,7 +63,8 @@ from contextlib import contextmanager
 
 import numpy as np
 
-SCHEDULES = ("classical", "t1", "hl", "ip", "ovr", "aclr", "accr", "acc", "ipmm")
+SCHEDULES = ("classical", "t1", "hl", "ip", "ovr", "aclr", "accr", "acc", "ipmm",
+             "blocked", "blocked_acc")
 OVERWRITES = {"ip": "AB", "ovr": "B", "aclr": "AB", "accr": "B"}
 
 
@@ -482,6 +490,26 @@ class Winograd:
             self._regions.pop()
         self.ipmm(A2, B2, C22, a, L, d + 1)
 
+    # --------------------------------------- Section 7.2 (blocked accumulation)
+    def blocked(self, core, A, B, C, a, b, t, L):
+        """Section 7.2: C <- a*A*B + b*C as a t x t grid of blocks; block C_ij
+        receives the t products A_il B_lj one after the other, each by one
+        accumulating call of ``core`` (Table 2 or Table 9) with depth L.  The
+        calls run one at a time, so the extra memory is that of one call on
+        an (n/t)-sized block."""
+        self.calls["blocked"] += 1
+        m, k = A.shape
+        n = B.shape[1]
+        ri, kl, cj = (_offsets(blocked_parts(d, t, L)) for d in (m, k, n))
+        kl = kl or [(0, 0)]             # k == 0: one empty product still scales C by b
+        for i0, i1 in ri:
+            for j0, j1 in cj:
+                Cij = C[i0:i1, j0:j1]
+                for l, (l0, l1) in enumerate(kl):
+                    bl = b if l == 0 else 1
+                    self.peeled(lambda A0, B0, C0, bl=bl: core(A0, B0, C0, a, bl, L),
+                                A[i0:i1, l0:l1], B[l0:l1, j0:j1], Cij, a, bl, L, True)
+
     # ------------------------------------------------------------ peeling
     def peeled(self, core, A, B, C, a, b, L, accumulate):
         """Winograd on the largest leading block whose dimensions are multiples
@@ -515,6 +543,33 @@ class Result:
         self.max_partial = w.max_partial
 
 
+def blocked_parts(d, t, L):
+    """Lengths of the t consecutive parts of a dimension of length d in the
+    blocked accumulation of Section 7.2: d/t each when t divides d, otherwise
+    ceil(d/t) rounded up to a multiple of 2**L with a shorter last part (and
+    fewer parts when d is small)."""
+    if d == 0:
+        return []
+    if d % t == 0:
+        return [d // t] * t
+    q = 2 ** L
+    s = -(-d // t)
+    s = -(-s // q) * q
+    parts = []
+    while d > 0:
+        parts.append(min(s, d))
+        d -= s
+    return parts
+
+
+def _offsets(parts):
+    out, o = [], 0
+    for x in parts:
+        out.append((o, o + x))
+        o += x
+    return out
+
+
 def ipmm_shape_ok(m, k, n, L):
     """Shapes Algorithm 2 can run with depth L under the chunking above."""
     if m != n or L < 0:
@@ -532,9 +587,13 @@ def ipmm_shape_ok(m, k, n, L):
     return True
 
 
-def _check(schedule, m, k, n, p, beta, L):
+def _check(schedule, m, k, n, p, beta, L, t=2):
     if schedule not in SCHEDULES:
         raise ValueError("unknown schedule %r" % (schedule,))
+    if schedule in ("blocked", "blocked_acc") and not 1 <= t <= 64:
+        raise ValueError("the block count t must lie in [1, 64]")
+    if schedule == "blocked_acc" and (not (m == k == n) or n % t):
+        raise ValueError("blocked accumulation over Table 9 needs m == k == n divisible by t")
     if beta % p and schedule in ("t1", "ip", "ovr", "ipmm"):
         raise ValueError("schedule %s computes C = A*B only (beta must be 0)" % schedule)
     if schedule in ("ip", "ovr", "aclr", "accr"):
@@ -547,7 +606,7 @@ def _check(schedule, m, k, n, p, beta, L):
         raise ValueError("shape not supported by ipmm at this depth")
 
 
-def _run(w, schedule, A, B, C, a, b, L):
+def _run(w, schedule, A, B, C, a, b, L, t=2):
     m, k = A.shape
     n = B.shape[1]
     p = w.p
@@ -569,16 +628,22 @@ def _run(w, schedule, A, B, C, a, b, L):
         w.accr(A, B, C, a, b, L)
     elif schedule == "ipmm":
         w.ipmm(A, B, C, a, L)
+    elif schedule == "blocked":
+        w.blocked(w.hl, A, B, C, a, b, t, L)
+    elif schedule == "blocked_acc":
+        w.blocked(w.acc, A, B, C, a, b, t, L)
 
 
 def replay(schedule, A, B, C=None, alpha=1, beta=0, p=65521, levels=1, *,
-           garbage_seed=None, kc=None):
+           garbage_seed=None, kc=None, blocks=2):
     """Run ``schedule`` on copies of the inputs; return a :class:`Result`.
 
     schedule: one of SCHEDULES.  'classical' is the plain product;
     't1', 'hl' and 'acc' peel remainders ('t1' and 'hl' also take
     rectangular shapes); 'ip', 'ovr', 'aclr', 'accr' need a square shape
-    divisible by 2**levels; 'ipmm' needs a square C (see ipmm_shape_ok)."""
+    divisible by 2**levels; 'ipmm' needs a square C (see ipmm_shape_ok);
+    'blocked' and 'blocked_acc' cut every dimension into ``blocks`` parts
+    ('blocked_acc' needs a square shape divisible by ``blocks``)."""
     p = int(p)
     w = Winograd(p, garbage_seed=garbage_seed, kc=kc)
     A = np.array(A, dtype=np.int64, copy=True)
@@ -590,22 +655,23 @@ def replay(schedule, A, B, C=None, alpha=1, beta=0, p=65521, levels=1, *,
         beta = 0
     else:
         C = np.array(C, dtype=np.int64, copy=True)
-    _check(schedule, m, k, n, p, int(beta), int(levels))
+    _check(schedule, m, k, n, p, int(beta), int(levels), int(blocks))
     if int(beta) % p == 0:
         w._garbage(C)                   # C is output only: its content is garbage
-    _run(w, schedule, A, B, C, int(alpha), int(beta), int(levels))
+    _run(w, schedule, A, B, C, int(alpha), int(beta), int(levels), int(blocks))
     return Result(C, A, B, w)
 
 
-def replay_shape(schedule, m, k, n, p=65521, levels=1, beta_nonzero=False):
+def replay_shape(schedule, m, k, n, p=65521, levels=1, beta_nonzero=False, blocks=2):
     """Follow ``schedule`` on shapes only (no arithmetic): counts and memory."""
     p = int(p)
     w = Winograd(p, dry=True)
     beta = 1 if beta_nonzero else 0
-    _check(schedule, m, k, n, p, beta, int(levels))
+    _check(schedule, m, k, n, p, beta, int(levels), int(blocks))
 
     def shaped(r, c):
         return np.lib.stride_tricks.as_strided(np.zeros(1, np.int64), (r, c), (0, 0))
 
-    _run(w, schedule, shaped(m, k), shaped(k, n), shaped(m, n), 1, beta, int(levels))
+    _run(w, schedule, shaped(m, k), shaped(k, n), shaped(m, n), 1, beta, int(levels),
+         int(blocks))
     return Result(None, None, None, w)

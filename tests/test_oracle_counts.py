@@ -9,13 +9,15 @@ and total allocated memory.  These are compared with
 * their closed forms at full recursion (Table 10, Theorem 1), including the
   two printed forms that do not solve their recurrences (recorded below),
 * Eq. (1), Eq. (2), Lemma 1 and the extra-memory bounds of Sections 5-6,
-* the allocation recurrences of Theorem 3 (Table 10's column).
+* the allocation recurrences of Theorem 3 (Table 10's column),
+* Section 7.2's R_t(n) and extra memory of the blocked accumulation.
 """
+import math
 from fractions import Fraction
 
 import pytest
 
-from oracle.schedules import fp64_chunk, replay, replay_shape
+from oracle.schedules import blocked_parts, fp64_chunk, replay, replay_shape
 
 
 # ----------------------------------------------------------- recurrences
@@ -257,3 +259,99 @@ def test_chunk_values():
     assert fp64_chunk(65521) == 2_098_176
     assert fp64_chunk(1048573) == 8192
     assert fp64_chunk(8388593) == 128
+
+
+# ------------------------------------------- Section 7.2: blocked accumulation
+@pytest.mark.parametrize("t", [1, 2, 3, 4])
+@pytest.mark.parametrize("e", range(1, 5))
+def test_blocked_rt_closed_form(t, e):
+    """R_t(n) = t^2 * t * W_acc(n/t) = 6 t^(3 - log7) n^log7 - 4 t n^2 at full
+    recursion of Table 2 on the (n/t)-blocks; with n = t 2^e,
+    t^(3 - log7) n^log7 = t^3 7^e exactly."""
+    n = t * 2**e
+    got = replay_shape("blocked", n, n, n, levels=e, beta_nonzero=True, blocks=t).ops
+    assert got == 6 * t**3 * 7**e - 4 * t * n * n
+    log7 = math.log2(7)
+    assert got == pytest.approx(6 * t ** (3 - log7) * n ** log7 - 4 * t * n * n, rel=1e-12)
+    assert got == t**3 * W2(n // t, e)
+
+
+def test_blocked_rt_constants():
+    """The leading constants quoted for t = 2 and t = 3 (6.857 and 7.414)."""
+    log7 = math.log2(7)
+    assert round(6 * 2 ** (3 - log7), 3) == 6.857
+    assert round(6 * 3 ** (3 - log7), 3) == 7.414
+
+
+@pytest.mark.parametrize("t,n", [(2, 64), (3, 48), (4, 64), (3, 96)])
+def test_blocked_classical_base_keeps_cubic_count(t, n):
+    """With no Winograd level the blocks are classical accumulations: the
+    t^3 calls of 2 (n/t)^3 operations give the classical 2 n^3."""
+    assert replay_shape("blocked", n, n, n, levels=0, beta_nonzero=True, blocks=t).ops == 2 * n**3
+    assert replay_shape("blocked_acc", n, n, n, levels=0, beta_nonzero=True, blocks=t).ops == 2 * n**3
+
+
+@pytest.mark.parametrize("t,e", [(2, 1), (2, 3), (3, 2), (3, 4), (4, 3)])
+def test_blocked_acc_base_count(t, e):
+    """Table 9 as the base: t^3 calls of Table 9 on (n/t)-blocks.  Table 9's
+    own rows give 6 m^log7 - 4 m^2 + m^2 (log^2 m + 7 log m) / 8 per call; the
+    extra term printed in Section 7.2 for this variant,
+    t^(2 - log3) n^log6 - t n^2 (t^3 (m^log6 - m^2)), is a different function
+    of m, like the printed Table 9 form checked above."""
+    n = t * 2**e
+    got = replay_shape("blocked_acc", n, n, n, levels=e, beta_nonzero=True, blocks=t).ops
+    assert got == t**3 * W9(n // t, e)
+    f7, f4 = 7**e, 4**e
+    own = t**3 * (6 * f7 - 4 * f4 + Fraction(f4, 8) * (e * e + 7 * e))
+    assert got == own
+    printed = t**3 * (6 * f7 - 4 * f4) + t**3 * (6**e - f4)
+    assert got != printed
+
+
+@pytest.mark.parametrize("t", [2, 3, 4])
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_blocked_extra_memory(t, l):
+    """One call's temporaries at a time: Table 2 on an (n/t)-block needs
+    3 (n/t)^2 (1 - 4^-l) / 3 = (n/t)^2 (1 - 4^-l), below the one chunk of
+    (n/t)^2 (n^2/4 for t = 2, n^2/9 for t = 3); Table 9 needs two thirds of
+    that, below 2 n^2 / (3 t^2)."""
+    n = t * 32
+    b = n // t
+    hl = replay_shape("blocked", n, n, n, levels=l, beta_nonzero=True, blocks=t).peak
+    assert hl == 3 * sum_quarters(b * b, l) == b * b * (1 - Fraction(1, 4**l))
+    assert hl < Fraction(n * n, t * t)
+    acc = replay_shape("blocked_acc", n, n, n, levels=l, beta_nonzero=True, blocks=t).peak
+    assert acc == 2 * sum_quarters(b * b, l)
+    assert acc < Fraction(2 * n * n, 3 * t * t)
+    # the unblocked schedules need t^2 times more
+    assert replay_shape("hl", n, n, n, levels=l, beta_nonzero=True).peak == t * t * hl
+    assert replay_shape("acc", n, n, n, levels=l, beta_nonzero=True).peak == t * t * acc
+
+
+def test_blocked_parts():
+    """The split of one dimension: n/t when t divides it, else ceil(n/t)
+    rounded up to a multiple of 2^L."""
+    assert blocked_parts(4096, 2, 3) == [2048, 2048]
+    assert blocked_parts(3000, 2, 3) == [1500, 1500]
+    assert blocked_parts(4096, 3, 3) == [1368, 1368, 1360]
+    assert blocked_parts(10, 3, 2) == [4, 4, 2]
+    assert blocked_parts(5, 3, 3) == [5]
+    assert blocked_parts(0, 3, 1) == []
+    for d in range(1, 70):
+        for t in (1, 2, 3, 5):
+            for L in (0, 1, 3):
+                parts = blocked_parts(d, t, L)
+                assert sum(parts) == d and 1 <= len(parts) <= t and min(parts) > 0
+                assert all(x % 2**L == 0 for x in parts[:-1]) or d % t == 0
+
+
+def test_blocked_workload_bytes():
+    """Extra bytes of the accumulating 4096^3 product with three levels: t = 2
+    and t = 3 blocks over Table 2 or Table 9, against the unblocked Table 9."""
+    b = lambda s, t: int(replay_shape(s, 4096, 4096, 4096, levels=3, beta_nonzero=True,
+                                      blocks=t).peak) * 8
+    assert b("blocked", 2) == 3 * (1024**2 + 512**2 + 256**2) * 8 == 33_030_144
+    assert b("blocked_acc", 2) == 2 * (1024**2 + 512**2 + 256**2) * 8 == 22_020_096
+    # parts 1368, 1368, 1360: the temporaries of the largest block
+    assert b("blocked", 3) == 3 * (684**2 + 342**2 + 171**2) * 8 == 14_737_464
+    assert b("acc", 2) == 88_080_384

@@ -220,3 +220,73 @@ def test_rejects_unsupported_shapes():
     A2, B2, _ = inputs.uniform(18, 12, 8, 16, P)
     with pytest.raises(ValueError):
         replay("aclr", A2, B2, np.zeros((12, 16), np.int64), 1, 1, P, 1)
+
+
+# ------------------------------------------- Section 7.2: blocked accumulation
+BLOCKED = [
+    # schedule, shape, levels, t
+    ("blocked", (64, 64, 64), 2, 2), ("blocked", (96, 96, 96), 1, 3),
+    ("blocked", (64, 32, 128), 2, 2), ("blocked", (37, 50, 29), 1, 3),
+    ("blocked", (100, 100, 100), 2, 3), ("blocked", (33, 17, 65), 2, 4),
+    ("blocked", (32, 32, 32), 2, 1), ("blocked", (5, 70, 3), 1, 3),
+    ("blocked_acc", (64, 64, 64), 2, 2), ("blocked_acc", (96, 96, 96), 2, 3),
+    ("blocked_acc", (90, 90, 90), 2, 3), ("blocked_acc", (64, 64, 64), 1, 4),
+]
+
+
+@pytest.mark.parametrize("p", [P, 8388593])
+@pytest.mark.parametrize("schedule,shape,levels,t", BLOCKED)
+def test_blocked_value_with_garbage(schedule, shape, levels, t, p):
+    m, k, n = shape
+    A, B, C = inputs.uniform(zlib.crc32(repr((schedule, shape, t)).encode()), m, k, n, p, True)
+    for seed, (alpha, beta) in enumerate([(1, 1), (3, p - 2), (p - 1, 5), (7, 0)]):
+        r = replay(schedule, A, B, C, alpha, beta, p, levels, garbage_seed=seed, blocks=t)
+        assert np.array_equal(r.C, o1(A, B, C, alpha, beta, p)), (alpha, beta)
+        assert np.array_equal(r.A, A) and np.array_equal(r.B, B)
+
+
+def test_blocked_empty_inner_dimension_scales_c():
+    A, B, C = inputs.uniform(21, 9, 0, 7, P, True)
+    r = replay("blocked", A, B, C, 4, 6, P, 1, blocks=3)
+    assert np.array_equal(r.C, 6 * C % P)
+
+
+class _BetaEveryCall(Winograd):
+    """A planted mistake: every inner block product applies beta again."""
+
+    def blocked(self, core, A, B, C, a, b, t, L):
+        from oracle.schedules import blocked_parts
+        m, k = A.shape
+        n = B.shape[1]
+        cut = lambda d: np.cumsum([0] + blocked_parts(d, t, L))
+        ri, kl, cj = cut(m), cut(k), cut(n)
+        for i in range(len(ri) - 1):
+            for j in range(len(cj) - 1):
+                for l in range(len(kl) - 1):
+                    core(A[ri[i]:ri[i + 1], kl[l]:kl[l + 1]], B[kl[l]:kl[l + 1], cj[j]:cj[j + 1]],
+                         C[ri[i]:ri[i + 1], cj[j]:cj[j + 1]], a, b, L)
+
+
+def test_blocked_planted_mistake_is_caught():
+    n = 32
+    A, B, C = inputs.uniform(22, n, n, n, P, True)
+    want = o1(A, B, C, 1, 3, P)
+    w = _BetaEveryCall(P, garbage_seed=0)
+    Cw = C.copy()
+    w.blocked(w.hl, A.copy(), B.copy(), Cw, 1, 3, 2, 1)
+    assert not np.array_equal(Cw, want)
+    w = Winograd(P, garbage_seed=0)
+    Cw = C.copy()
+    w.blocked(w.hl, A.copy(), B.copy(), Cw, 1, 3, 2, 1)
+    assert np.array_equal(Cw, want)
+
+
+def test_blocked_rejects_bad_blocks():
+    A, B, C = inputs.uniform(23, 12, 12, 12, P, True)
+    with pytest.raises(ValueError):
+        replay("blocked", A, B, C, 1, 1, P, 1, blocks=0)
+    with pytest.raises(ValueError):
+        replay("blocked_acc", A, B, C, 1, 1, P, 1, blocks=5)     # 12 not divisible by 5
+    A2, B2, C2 = inputs.uniform(24, 12, 8, 12, P, True)
+    with pytest.raises(ValueError):
+        replay("blocked_acc", A2, B2, C2, 1, 1, P, 1, blocks=2)  # not square
