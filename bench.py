@@ -15,6 +15,10 @@ product.
   t1_16384_p1048573             C = A*B mod 1048573, 16384^3, schedule, depth and base
                                 chosen by the autotuner, against the binary64 and 8-bit
                                 digit bases under fixed schedules
+  acc_4096_p65521_blocked       the default product under Section 7.2's blocked accumulation:
+                                C in t x t blocks (--blocks, default 2), each block by t
+                                Table 9 calls of two levels, extra memory below 2(n/t)^2/3;
+                                against unblocked Table 9, the Table 2 base and classical
   batch_2000                    2000 products, sizes log-uniform in [64, 2048], moduli
                                 from {65521, 1048573, 8388593}, autotuned, one hipGraph
                                 replay of the persistent batched launches
@@ -43,9 +47,12 @@ METRIC = "mod-p matmul effective Gop/s (2mnk/s) + peak temp bytes vs classical m
 SCHEDULE_NAMES = {0: "classical", 1: "two temporaries (Table 1 / Table 9)",
                   2: "input-overwriting (Table 3 / Table 6)",
                   3: "read-only in place (Algorithm 2)", 4: "three temporaries (Table 2)",
-                  6: "overwrite, accumulate right (Table 5)", 7: "accumulate right (Table 7)"}
+                  6: "overwrite, accumulate right (Table 5)", 7: "accumulate right (Table 7)",
+                  8: "blocked accumulation over Table 2 (Section 7.2)",
+                  9: "blocked accumulation over Table 9 (Section 7.2)"}
 WORKLOADS = ("acc_4096_p65521_l3", "t1_512_p65521_l1_i64", "ipmm_8192x4096x8192_p8388593",
-             "t1_16384_p1048573", "batch_2000")
+             "t1_16384_p1048573", "acc_4096_p65521_blocked", "batch_2000")
+INPUTS_OF = {"acc_4096_p65521_blocked": "acc_4096_p65521_l3"}   # same product, other schedule
 
 
 def log(msg):
@@ -209,7 +216,7 @@ def single_product(ctx, name):
     """The four single-product workloads."""
     capi, inputs, torch = ctx.capi, ctx.inputs, ctx.torch
     a = ctx.args
-    w = inputs.WORKLOADS[name]
+    w = inputs.WORKLOADS[INPUTS_OF.get(name, name)]
     m, k, n, p = w["m"], w["k"], w["n"], w["p"]
     alpha, beta = w["alpha"], w["beta"]
     i64 = w["dtype"] == "i64"
@@ -223,12 +230,13 @@ def single_product(ctx, name):
     dC = ctx.to_dev(C) if C is not None else torch.zeros((m, n), dtype=dA.dtype, device=ctx.dev)
     flops = 2.0 * m * n * k
 
-    def mkargs(schedule, levels, base=capi.WS_BASE_F64_MFMA, ws=None, nbytes=0):
+    def mkargs(schedule, levels, base=capi.WS_BASE_F64_MFMA, ws=None, nbytes=0, blocks=0):
         return capi.make_args(m, k, n, p, dA, dB, dC, alpha, beta, schedule, levels, dtype=dt,
-                              base=base, stream=ctx.stream, workspace=ws, workspace_bytes=nbytes)
+                              base=base, stream=ctx.stream, workspace=ws, workspace_bytes=nbytes,
+                              blocks=blocks)
 
-    def ws_for(schedule, levels):
-        nbytes = capi.wsmul_workspace_bytes(m, k, n, dt, schedule, levels, int(beta != 0))
+    def ws_for(schedule, levels, blocks=0):
+        nbytes = capi.wsmul_plan_info(mkargs(schedule, levels, blocks=blocks)).workspace_bytes
         return torch.empty(max(nbytes // 8, 1), dtype=torch.float64, device=ctx.dev), nbytes
 
     def run(args):
@@ -236,12 +244,20 @@ def single_product(ctx, name):
 
     extra = {}
     int8 = False
+    blocks = 0
+    lev_or = lambda d: d if a.levels is None else a.levels
     if name == "acc_4096_p65521_l3":
-        sched, lev, base, label = capi.WS_TWO_TEMP, a.levels, capi.WS_BASE_F64_MFMA, \
+        sched, lev, base, label = capi.WS_TWO_TEMP, lev_or(3), capi.WS_BASE_F64_MFMA, \
             "table9-accumulate-two-temporaries"
         config = {"workload": name, "m": m, "k": k, "n": n, "p": p, "op": "C <- A*B + C",
                   "schedule": label, "levels": lev, "base": "f64 matrix cores",
                   "parallelism": "single GPU"}
+    elif name == "acc_4096_p65521_blocked":
+        sched, lev, base, blocks = capi.WS_BLOCKED_ACC, lev_or(2), capi.WS_BASE_F64_MFMA, \
+            a.blocks
+        config = {"workload": name, "m": m, "k": k, "n": n, "p": p, "op": "C <- A*B + C",
+                  "schedule": "section7.2-blocked-accumulation-table9", "blocks": blocks,
+                  "levels": lev, "base": "f64 matrix cores", "parallelism": "single GPU"}
     elif name == "t1_512_p65521_l1_i64":
         sched, lev, base = capi.WS_TWO_TEMP, 1, capi.WS_BASE_F64_MFMA
         config = {"workload": name, "m": m, "k": k, "n": n, "p": p, "op": "C = A*B",
@@ -253,8 +269,8 @@ def single_product(ctx, name):
                   "schedule": "algorithm2-readonly-inplace", "levels": lev,
                   "base": "f64 matrix cores", "parallelism": "single GPU"}
     else:   # t1_16384_p1048573: the autotuner decides
-        st, sched, lev, base = capi.wsmul_autotune(m, k, n, p, dt, 2 ** 62, capi.WS_AUTO, -1,
-                                                   capi.WS_BASE_AUTO, beta)
+        st, sched, lev, base, _ = capi.wsmul_autotune(m, k, n, p, dt, 2 ** 62, capi.WS_AUTO, -1,
+                                                      capi.WS_BASE_AUTO, beta)
         capi.check(st)
         int8 = base == capi.WS_BASE_I8_LIMBS
         config = {"workload": name, "m": m, "k": k, "n": n, "p": p, "op": "C = A*B",
@@ -263,8 +279,8 @@ def single_product(ctx, name):
                   "base": "int8 digits (3 balanced base-256 digits)" if int8
                   else "f64 matrix cores", "parallelism": "single GPU"}
 
-    ws, nbytes = ws_for(sched, lev)
-    head = mkargs(sched, lev, base, ws, nbytes)
+    ws, nbytes = ws_for(sched, lev, blocks)
+    head = mkargs(sched, lev, base, ws, nbytes, blocks)
     steps, warmup = a.steps, a.warmup
     log("timing %d steps (%s, %d levels)" % (steps, config["schedule"], lev))
     ms_step = ctx.timed(lambda: run(head), steps, warmup)
@@ -281,9 +297,10 @@ def single_product(ctx, name):
     if not a.no_compare:
         reps = max(3, steps // 2)
 
-        def compare(key, schedule, levels, base=capi.WS_BASE_F64_MFMA, restore=False):
-            w2, nb2 = ws_for(schedule, levels) if schedule != capi.WS_CLASSICAL else (None, 0)
-            args2 = mkargs(schedule, levels, base, w2, nb2)
+        def compare(key, schedule, levels, base=capi.WS_BASE_F64_MFMA, restore=False, blocks=0):
+            w2, nb2 = (ws_for(schedule, levels, blocks) if schedule != capi.WS_CLASSICAL
+                       else (None, 0))
+            args2 = mkargs(schedule, levels, base, w2, nb2, blocks)
             run(args2)
             torch.cuda.synchronize()
             before = None
@@ -305,6 +322,11 @@ def single_product(ctx, name):
             compare("overwrite_table6", capi.WS_OVERWRITE, lev, restore=True)
         elif name == "ipmm_8192x4096x8192_p8388593":
             compare("two_temporaries_table1", capi.WS_TWO_TEMP, 1)
+        elif name == "acc_4096_p65521_blocked":
+            compare("table9_unblocked_3_levels", capi.WS_TWO_TEMP, 3)
+            compare("blocked_t2_table2_2_levels", capi.WS_BLOCKED, 2, blocks=2)
+            compare("blocked_t3_table2_2_levels", capi.WS_BLOCKED, 2, blocks=3)
+            compare("blocked_t4_table9_1_level", capi.WS_BLOCKED_ACC, 1, blocks=4)
         elif name == "t1_16384_p1048573":
             compare("classical_int8_digits", capi.WS_CLASSICAL, 0, capi.WS_BASE_I8_LIMBS)
             compare("table1_1_level_int8_digits", capi.WS_TWO_TEMP, 1, capi.WS_BASE_I8_LIMBS)
@@ -394,8 +416,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--levels", type=int, default=3,
-                    help="Winograd levels of the default workload")
+    ap.add_argument("--levels", type=int, default=None,
+                    help="Winograd levels of the accumulating 4096^3 workloads "
+                         "(default 3 unblocked, 2 blocked)")
+    ap.add_argument("--blocks", type=int, default=2,
+                    help="t of the blocked accumulation workload")
     ap.add_argument("--workload", default=WORKLOADS[0], choices=WORKLOADS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparator schedules")

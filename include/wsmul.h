@@ -69,8 +69,28 @@ typedef enum {
     WS_HL_THREE_TEMP = 4,    /* Table 2 (three temporaries, any beta)              */
     WS_AUTO = 5,             /* schedule, depth and base chosen by the autotuner   */
     WS_OVR = 6,              /* Table 5: C = A*B, one temporary, destroys B        */
-    WS_ACCR = 7              /* Table 7: two temporaries, destroys B (square)      */
+    WS_ACCR = 7,             /* Table 7: two temporaries, destroys B (square)      */
+    WS_BLOCKED = 8,          /* Section 7.2 over Table 2: C in t x t blocks, see below */
+    WS_BLOCKED_ACC = 9       /* Section 7.2 over Table 9 (m == k == n, t | n)      */
 } ws_schedule;
+
+/*
+ * Blocked accumulation (Section 7.2).  A, B and C are cut along every
+ * dimension into t = ws_args.blocks consecutive parts (n/t each when t
+ * divides the dimension; otherwise ceil(n/t) rounded up to a multiple of
+ * 2^levels, with a shorter last part).  Block C_ij accumulates the t products
+ * A_il * B_lj in order of l, the first with beta and the others with 1, each
+ * by one call of the base schedule with `levels` levels: Table 2 for
+ * WS_BLOCKED (any shape), Table 9 for WS_BLOCKED_ACC (square blocks).  The
+ * calls run one after the other and share one set of temporaries, so the
+ * extra memory is that of a single call on an (n/t)-block: below (n/t)^2 for
+ * Table 2 (n^2/4 at t = 2, n^2/9 at t = 3) and below 2(n/t)^2/3 for Table 9,
+ * against n^2 and 2n^2/3 unblocked.  The arithmetic grows to
+ * R_t(n) = t^3 W_acc(n/t) (Section 7.2).  A and B are read only; any beta.
+ * blocks = 0 means t = 2; t lies in [1, 64].  The other schedules ignore
+ * ws_args.blocks; wsmul_mod_p, wsmul_mod_p_i64 and wsmul_workspace_bytes use
+ * t = 2 (wsmul_plan_info reports any t).
+ */
 
 typedef enum { WS_F64 = 0, WS_I64 = 1 } ws_dtype;
 
@@ -101,7 +121,7 @@ typedef struct ws_args {
     uint64_t workspace_bytes;
     void *stream;              /* hipStream_t; NULL: the stream from wsmul_set_stream */
     uint32_t flags;
-    uint32_t reserved;
+    uint32_t blocks;           /* WS_BLOCKED / WS_BLOCKED_ACC: t (0 means 2)        */
 } ws_args;
 
 /* Counters of the most recent call on this thread. */
@@ -125,8 +145,8 @@ typedef struct ws_stats {
 /*
  * The spec call: binary64 storage, dense leading dimensions, default
  * stream and workspace.  C <- (alpha*A*B + beta*C) mod p with `levels`
- * Winograd levels under `schedule` (Section 3.2; schedules of Tables 1-9 and
- * Algorithm 2).
+ * Winograd levels under `schedule` (Section 3.2; schedules of Tables 1-9,
+ * Algorithm 2 and the blocked accumulation of Section 7.2).
  */
 WSMUL_API int wsmul_mod_p(int64_t m, int64_t k, int64_t n, int64_t p,
                 void *A, void *B, void *C, int64_t alpha, int64_t beta,
@@ -143,7 +163,8 @@ WSMUL_API int wsmul_mod_p_ex(const ws_args *args);
 /*
  * Bytes of temporaries the schedule needs (its "extra memory": Eq. (1) for
  * Table 1, Eq. (2) for Table 2, the bounds of Sections 5-6 for Tables 5-9,
- * zero for Table 3 and Algorithm 2), for dense binary64 or int64 storage.
+ * zero for Table 3 and Algorithm 2, one (n/t)-block call for Section 7.2 with
+ * t = 2), for dense binary64 or int64 storage.
  * Returns 0 for unsupported combinations (check wsmul_last_error()).
  */
 WSMUL_API size_t wsmul_workspace_bytes(int64_t m, int64_t k, int64_t n, int dtype, int schedule,

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libwsmul.so")
 WS_OK, WS_EINVAL, WS_ESHAPE, WS_EMODULUS, WS_ERANGE, WS_ESCHEDULE, WS_ENOMEM, WS_EHIP = range(8)
 # ws_schedule
 (WS_CLASSICAL, WS_TWO_TEMP, WS_OVERWRITE, WS_READONLY_INPLACE, WS_HL_THREE_TEMP, WS_AUTO,
- WS_OVR, WS_ACCR) = range(8)
+ WS_OVR, WS_ACCR, WS_BLOCKED, WS_BLOCKED_ACC) = range(10)
 WS_F64, WS_I64 = 0, 1
 WS_BASE_AUTO, WS_BASE_F64_MFMA, WS_BASE_I8_LIMBS = 0, 1, 2
 WS_FLAG_CHECK, WS_FLAG_NOFUSE, WS_FLAG_TRACE, WS_FLAG_SYNC = 1, 2, 4, 8
@@ -26,7 +26,8 @@ WS_OP_ADD, WS_OP_GEMM = 0, 1
 
 SCHEDULES = {"classical": WS_CLASSICAL, "two_temp": WS_TWO_TEMP, "overwrite": WS_OVERWRITE,
              "readonly_inplace": WS_READONLY_INPLACE, "hl_three_temp": WS_HL_THREE_TEMP,
-             "auto": WS_AUTO, "ovr": WS_OVR, "accr": WS_ACCR}
+             "auto": WS_AUTO, "ovr": WS_OVR, "accr": WS_ACCR, "blocked": WS_BLOCKED,
+             "blocked_acc": WS_BLOCKED_ACC}
 
 _i64, _i32, _u32, _u64, _vp, _dbl = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
                                      ctypes.c_uint64, ctypes.c_void_p, ctypes.c_double)
@@ -39,7 +40,7 @@ class ws_args(ctypes.Structure):
                 ("A", _vp), ("B", _vp), ("C", _vp),
                 ("dtype", _i32), ("schedule", _i32), ("levels", _i32), ("base", _i32),
                 ("workspace", _vp), ("workspace_bytes", _u64),
-                ("stream", _vp), ("flags", _u32), ("reserved", _u32)]
+                ("stream", _vp), ("flags", _u32), ("blocks", _u32)]
 
 
 class ws_stats(ctypes.Structure):
@@ -165,7 +166,7 @@ def wsmul_mod_p_i64(m, k, n, p, A, B, C, alpha, beta, schedule, levels):
 
 def make_args(m, k, n, p, A=None, B=None, C=None, alpha=1, beta=0, schedule=WS_TWO_TEMP,
               levels=1, dtype=WS_F64, base=WS_BASE_F64_MFMA, lda=0, ldb=0, ldc=0,
-              workspace=None, workspace_bytes=0, stream=None, flags=0):
+              workspace=None, workspace_bytes=0, stream=None, flags=0, blocks=0):
     a = ws_args()
     a.m, a.k, a.n, a.p = m, k, n, p
     a.lda, a.ldb, a.ldc = lda, ldb, ldc
@@ -175,6 +176,7 @@ def make_args(m, k, n, p, A=None, B=None, C=None, alpha=1, beta=0, schedule=WS_T
     a.workspace, a.workspace_bytes = _ptr(workspace), workspace_bytes
     a.stream = _stream(stream)
     a.flags = flags
+    a.blocks = blocks
     return a
 
 
@@ -257,9 +259,9 @@ def wsmul_graph_destroy(handle):
 
 
 def wsmul_autotune(m, k, n, p, dtype=WS_F64, mem_budget=(1 << 64) - 1, schedule=WS_AUTO,
-                   levels=-1, base=WS_BASE_AUTO, beta=0):
-    """Return (status, schedule, levels, base) chosen for one product."""
+                   levels=-1, base=WS_BASE_AUTO, beta=0, blocks=0):
+    """Return (status, schedule, levels, base, blocks) chosen for one product."""
     c = ws_args()
-    c.schedule, c.levels, c.base, c.beta = schedule, levels, base, beta
+    c.schedule, c.levels, c.base, c.beta, c.blocks = schedule, levels, base, beta, blocks
     st = lib().wsmul_autotune(m, k, n, p, dtype, mem_budget, ctypes.byref(c))
-    return st, c.schedule, c.levels, c.base
+    return st, c.schedule, c.levels, c.base, c.blocks

@@ -13,6 +13,10 @@
 //   addition groups: bytes moved at 4.5 TB/s, 4 us floor per launch.
 // The cheapest candidate whose temporaries fit the memory budget wins.
 // Overwriting schedules are never chosen automatically (they destroy A, B).
+// For accumulating products the blocked accumulation of Section 7.2 (t = 2,
+// 3, 4 over Table 2, or over Table 9 when square) is a candidate too: it is
+// never the fastest, but it keeps Winograd's saving when the budget is below
+// the unblocked schedules' temporaries.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -59,15 +63,16 @@ double gemm_digits_us(int64_t M, int64_t N, int64_t K) {
 
 struct Key {
     int64_t m, k, n, p;
-    int dtype, beta_nz, schedule, levels, base;
+    int dtype, beta_nz, schedule, levels, base, blocks;
     size_t budget;
     bool operator<(const Key &o) const {
-        return std::tie(m, k, n, p, dtype, beta_nz, schedule, levels, base, budget) <
-               std::tie(o.m, o.k, o.n, o.p, o.dtype, o.beta_nz, o.schedule, o.levels, o.base, o.budget);
+        return std::tie(m, k, n, p, dtype, beta_nz, schedule, levels, base, blocks, budget) <
+               std::tie(o.m, o.k, o.n, o.p, o.dtype, o.beta_nz, o.schedule, o.levels, o.base,
+                        o.blocks, o.budget);
     }
 };
 struct Choice {
-    int schedule, levels, base;
+    int schedule, levels, base, blocks;
     double cost_us;
 };
 
@@ -96,10 +101,11 @@ void load_cache() {
         if (std::sscanf(line,
                         "{\"m\": %lld, \"k\": %lld, \"n\": %lld, \"p\": %lld, \"dtype\": %d, "
                         "\"beta_nz\": %d, \"schedule_in\": %d, \"levels_in\": %d, \"base_in\": %d, "
-                        "\"budget\": %llu, \"schedule\": %d, \"levels\": %d, \"base\": %d, "
-                        "\"cost_us\": %lf}",
+                        "\"blocks_in\": %d, \"budget\": %llu, \"schedule\": %d, \"levels\": %d, "
+                        "\"base\": %d, \"blocks\": %d, \"cost_us\": %lf}",
                         &m, &kk, &n, &p, &k.dtype, &k.beta_nz, &k.schedule, &k.levels, &k.base,
-                        &budget, &c.schedule, &c.levels, &c.base, &c.cost_us) == 14) {
+                        &k.blocks, &budget, &c.schedule, &c.levels, &c.base, &c.blocks,
+                        &c.cost_us) == 16) {
             k.m = m;
             k.k = kk;
             k.n = n;
@@ -121,11 +127,11 @@ void save_entry(const Key &k, const Choice &c) {
     std::fprintf(f,
                  "{\"m\": %lld, \"k\": %lld, \"n\": %lld, \"p\": %lld, \"dtype\": %d, "
                  "\"beta_nz\": %d, \"schedule_in\": %d, \"levels_in\": %d, \"base_in\": %d, "
-                 "\"budget\": %llu, \"schedule\": %d, \"levels\": %d, \"base\": %d, "
-                 "\"cost_us\": %.3f}\n",
+                 "\"blocks_in\": %d, \"budget\": %llu, \"schedule\": %d, \"levels\": %d, "
+                 "\"base\": %d, \"blocks\": %d, \"cost_us\": %.3f}\n",
                  (long long)k.m, (long long)k.k, (long long)k.n, (long long)k.p, k.dtype, k.beta_nz,
-                 k.schedule, k.levels, k.base, (unsigned long long)k.budget, c.schedule, c.levels,
-                 c.base, c.cost_us);
+                 k.schedule, k.levels, k.base, k.blocks, (unsigned long long)k.budget, c.schedule,
+                 c.levels, c.base, c.blocks, c.cost_us);
     std::fclose(f);
 }
 
@@ -133,23 +139,26 @@ void save_entry(const Key &k, const Choice &c) {
 bool search(const Key &key, Choice &best) {
     bool found = false;
     best.cost_us = 1e300;
-    const int64_t mn = std::min(key.m, std::min(key.k, key.n));
-    int max_l = 0;
-    while (max_l < 5 && (mn >> (max_l + 1)) >= 64)
-        ++max_l;
-    std::vector<int> schedules;
-    if (key.schedule != WS_AUTO)
-        schedules.push_back(key.schedule);
-    else {
+    // (schedule, t) pairs; t only matters for the blocked schedules.
+    std::vector<std::pair<int, int>> cands;
+    if (key.schedule != WS_AUTO) {
+        cands.push_back({key.schedule, key.blocks});
+    } else {
         // Read-only candidates: classical, the two-temporary schedules
-        // (Table 1 / Table 9), Algorithm 2 for C = A*B, and Table 2 for
-        // accumulating products that Table 9 cannot take (non-square).
-        schedules.push_back(WS_CLASSICAL);
-        schedules.push_back(WS_TWO_TEMP);
-        if (!key.beta_nz)
-            schedules.push_back(WS_READONLY_INPLACE);
-        else
-            schedules.push_back(WS_HL_THREE_TEMP);
+        // (Table 1 / Table 9), Algorithm 2 for C = A*B; for accumulating
+        // products also Table 2 (non-square shapes) and the blocked
+        // accumulation of Section 7.2 (small memory budgets).
+        cands.push_back({WS_CLASSICAL, 0});
+        cands.push_back({WS_TWO_TEMP, 0});
+        if (!key.beta_nz) {
+            cands.push_back({WS_READONLY_INPLACE, 0});
+        } else {
+            cands.push_back({WS_HL_THREE_TEMP, 0});
+            for (int t : {2, 3, 4}) {
+                cands.push_back({WS_BLOCKED, t});
+                cands.push_back({WS_BLOCKED_ACC, t});
+            }
+        }
     }
     std::vector<int> bases;
     if (key.base != WS_BASE_AUTO)
@@ -159,11 +168,19 @@ bool search(const Key &key, Choice &best) {
         if (limbs_supported(key.p) && key.k <= 32768 && key.k > 0)
             bases.push_back(WS_BASE_I8_LIMBS);
     }
-    for (int sched : schedules) {
+    const int64_t mn = std::min(key.m, std::min(key.k, key.n));
+    for (const auto &cand : cands) {
+        const int sched = cand.first, t = cand.second;
+        const bool blocked = sched == WS_BLOCKED || sched == WS_BLOCKED_ACC;
+        // deepest level that keeps base products of at least 64 (per block)
+        const int64_t mb = blocked ? mn / std::max(t, 1) : mn;
+        int top = 0;
+        while (top < 5 && (mb >> (top + 1)) >= 64)
+            ++top;
         const int lo = key.levels >= 0 ? key.levels : (sched == WS_CLASSICAL ? 0 : 1);
-        const int hi = key.levels >= 0 ? key.levels : (sched == WS_CLASSICAL ? 0 : max_l);
+        const int hi = key.levels >= 0 ? key.levels : (sched == WS_CLASSICAL ? 0 : top);
         for (int l = lo; l <= hi; ++l) {
-            const Resolved r = resolve_schedule(sched, key.m, key.k, key.n, key.beta_nz != 0, l);
+            const Resolved r = resolve_schedule(sched, key.m, key.k, key.n, key.beta_nz != 0, l, t);
             if (r.status != WS_OK)
                 continue;
             PlanKey pk{};
@@ -180,6 +197,7 @@ bool search(const Key &key, Choice &best) {
             pk.table = r.table;
             pk.levels = r.levels;
             pk.fuse = 1;
+            pk.blocks = blocked ? t : 0;
             std::shared_ptr<Plan> plan;
             try {
                 plan = get_plan(pk);
@@ -191,7 +209,7 @@ bool search(const Key &key, Choice &best) {
             for (int base : bases) {
                 const double c = plan_cost_us(*plan, base);
                 if (c < best.cost_us) {
-                    best = Choice{sched, l, base, c};
+                    best = Choice{sched, l, base, blocked ? t : key.blocks, c};
                     found = true;
                 }
             }
@@ -230,6 +248,7 @@ int autotune_choice(ws_args &a, bool beta_nonzero) {
     a.schedule = c.schedule;
     a.levels = c.levels;
     a.base = c.base;
+    a.blocks = c.blocks;
     return WS_OK;
 }
 
@@ -245,11 +264,13 @@ extern "C" int wsmul_autotune(int64_t m, int64_t k, int64_t n, int64_t p, int dt
         return WS_EINVAL;
     }
     const bool beta_nz = ((choice->beta % p) + p) % p != 0;
+    const int blocks = choice->blocks == 0 ? 2 : (int)std::min<uint32_t>(choice->blocks, 1u << 20);
     Key key{m, k, n, p, dtype, beta_nz ? 1 : 0, choice->schedule, choice->levels, choice->base,
-            mem_budget};
+            blocks, mem_budget};
     if (key.schedule != WS_AUTO && key.schedule != WS_CLASSICAL && key.schedule != WS_TWO_TEMP &&
         key.schedule != WS_OVERWRITE && key.schedule != WS_READONLY_INPLACE &&
-        key.schedule != WS_HL_THREE_TEMP && key.schedule != WS_OVR && key.schedule != WS_ACCR) {
+        key.schedule != WS_HL_THREE_TEMP && key.schedule != WS_OVR && key.schedule != WS_ACCR &&
+        key.schedule != WS_BLOCKED && key.schedule != WS_BLOCKED_ACC) {
         set_error("wsmul_autotune: unknown schedule");
         return WS_ESCHEDULE;
     }
@@ -257,6 +278,7 @@ extern "C" int wsmul_autotune(int64_t m, int64_t k, int64_t n, int64_t p, int dt
         choice->schedule = key.schedule == WS_AUTO ? WS_CLASSICAL : key.schedule;
         choice->levels = 0;
         choice->base = key.base == WS_BASE_AUTO ? WS_BASE_F64_MFMA : key.base;
+        choice->blocks = (uint32_t)blocks;
         return WS_OK;
     }
     Choice best{};
@@ -269,6 +291,7 @@ extern "C" int wsmul_autotune(int64_t m, int64_t k, int64_t n, int64_t p, int dt
             choice->schedule = best.schedule;
             choice->levels = best.levels;
             choice->base = best.base;
+            choice->blocks = (uint32_t)best.blocks;
             return WS_OK;
         }
     }
@@ -284,5 +307,6 @@ extern "C" int wsmul_autotune(int64_t m, int64_t k, int64_t n, int64_t p, int dt
     choice->schedule = best.schedule;
     choice->levels = best.levels;
     choice->base = best.base;
+    choice->blocks = (uint32_t)best.blocks;
     return WS_OK;
 }

@@ -30,7 +30,7 @@ hipStream_t g_stream = nullptr;
 struct KeyHash {
     size_t operator()(const PlanKey &k) const {
         const int64_t v[] = {k.m, k.k, k.n, k.p, k.lda, k.ldb, k.ldc, k.alpha, k.beta,
-                             k.dtype, k.table, k.levels, k.fuse};
+                             k.dtype, k.table, k.levels, k.fuse, k.blocks};
         uint64_t h = 1469598103934665603ull;
         for (int64_t x : v) {
             h ^= (uint64_t)x;
@@ -111,6 +111,8 @@ int prepare(const ws_args *in, ws_args &a, PlanKey &key, Resolved &res) {
     if (a.base != WS_BASE_AUTO && a.base != WS_BASE_F64_MFMA && a.base != WS_BASE_I8_LIMBS)
         return fail(WS_EINVAL, "unknown base kind");
     const bool beta_nz = canon(a.beta, a.p) != 0;
+    if (a.blocks == 0)
+        a.blocks = 2;
     if (a.schedule == WS_AUTO || a.levels < 0 || a.base == WS_BASE_AUTO) {
         const int rc = autotune_choice(a, beta_nz);
         if (rc != WS_OK)
@@ -122,7 +124,8 @@ int prepare(const ws_args *in, ws_args &a, PlanKey &key, Resolved &res) {
         return fail(WS_EMODULUS, "p too large for three signed 8-bit digits (p <= 16711423)");
     if (a.base == WS_BASE_I8_LIMBS && a.k > 32768)
         return fail(WS_ESHAPE, "the 8-bit digit base needs k <= 32768 (exact int32 sums)");
-    res = resolve_schedule(a.schedule, a.m, a.k, a.n, beta_nz, a.levels);
+    res = resolve_schedule(a.schedule, a.m, a.k, a.n, beta_nz, a.levels,
+                           (int)std::min<uint32_t>(a.blocks, 1u << 20));
     if (res.status != WS_OK)
         return fail(res.status, res.error);
     std::memset(&key, 0, sizeof(key));
@@ -139,6 +142,7 @@ int prepare(const ws_args *in, ws_args &a, PlanKey &key, Resolved &res) {
     key.table = res.table;
     key.levels = res.levels;
     key.fuse = (a.flags & WS_FLAG_NOFUSE) ? 0 : 1;
+    key.blocks = (res.table == TAB_BLOCKED_HL || res.table == TAB_BLOCKED_ACC) ? (int32_t)a.blocks : 0;
     return WS_OK;
 }
 
@@ -477,6 +481,8 @@ const char *wsmul_schedule_name(int table) {
     case TAB_ACCR: return "table7-accumulate-overwrite-B";
     case TAB_ACC: return "table9-accumulate-two-temporaries";
     case TAB_IPMM: return "algorithm2-read-only-in-place";
+    case TAB_BLOCKED_HL: return "section7.2-blocked-accumulation-table2";
+    case TAB_BLOCKED_ACC: return "section7.2-blocked-accumulation-table9";
     default: return "unknown";
     }
 }

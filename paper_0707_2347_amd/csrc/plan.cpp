@@ -18,7 +18,7 @@ namespace wsmul {
 bool PlanKey::operator==(const PlanKey &o) const {
     return m == o.m && k == o.k && n == o.n && p == o.p && lda == o.lda && ldb == o.ldb &&
            ldc == o.ldc && alpha == o.alpha && beta == o.beta && dtype == o.dtype &&
-           table == o.table && levels == o.levels && fuse == o.fuse;
+           table == o.table && levels == o.levels && fuse == o.fuse && blocks == o.blocks;
 }
 
 namespace {
@@ -639,6 +639,40 @@ class Emitter {
         ipmm(A2, B2, C22, a, L, dd + 1);
     }
 
+    // ---- Section 7.2: C <- a*A*B + b*C as a t x t grid of blocks.  Block
+    // C_ij receives the t products A_il B_lj one after the other, each by one
+    // accumulating call of Table 2 (or Table 9 for square blocks), the first
+    // with b and the others with 1.  Every call sits at depth 0, so all of
+    // them share the same workspace slots: the extra memory is that of one
+    // call on an (n/t)-block.
+    void blocked(bool acc_base, View A, View B, View C, int64_t a, int64_t b, int t, int L) {
+        const std::vector<int64_t> rp = block_parts(A.rows, t, L), cp = block_parts(B.cols, t, L);
+        std::vector<int64_t> kp = block_parts(A.cols, t, L);
+        if (kp.empty())
+            kp.push_back(0);   // k == 0: one empty product still scales C by b
+        int64_t r0 = 0;
+        for (int64_t rl : rp) {
+            int64_t c0 = 0;
+            for (int64_t cl : cp) {
+                const View Cij = block(C, r0, c0, rl, cl);
+                int64_t k0 = 0;
+                for (size_t l = 0; l < kp.size(); ++l) {
+                    const int64_t kl = kp[l], bl = l == 0 ? b : 1;
+                    const View Ail = block(A, r0, k0, rl, kl), Blj = block(B, k0, c0, kl, cl);
+                    if (acc_base)
+                        peeled([&](View A0, View B0, View C0) { acc(A0, B0, C0, a, bl, L, 0); },
+                               Ail, Blj, Cij, a, bl, L);
+                    else
+                        peeled([&](View A0, View B0, View C0) { hl(A0, B0, C0, a, bl, L, 0); },
+                               Ail, Blj, Cij, a, bl, L);
+                    k0 += kl;
+                }
+                c0 += cl;
+            }
+            r0 += rl;
+        }
+    }
+
     // ---- peeling: Winograd on the leading block whose dimensions are
     // multiples of 2^L, classical products for the thin remainders.
     template <typename Core>
@@ -702,6 +736,10 @@ void run(Emitter &e, const PlanKey &key) {
     case TAB_IPMM:
         e.ipmm(A, B, C, a, L, 0);
         break;
+    case TAB_BLOCKED_HL:
+    case TAB_BLOCKED_ACC:
+        e.blocked(key.table == TAB_BLOCKED_ACC, A, B, C, a, b, key.blocks, L);
+        break;
     default:
         throw std::logic_error("unknown table");
     }
@@ -709,6 +747,20 @@ void run(Emitter &e, const PlanKey &key) {
 }
 
 }  // namespace
+
+std::vector<int64_t> block_parts(int64_t d, int t, int L) {
+    std::vector<int64_t> out;
+    if (d <= 0 || t < 1)
+        return out;
+    if (d % t == 0)
+        return std::vector<int64_t>((size_t)t, d / t);
+    const int64_t q = int64_t(1) << L;
+    int64_t s = (d + t - 1) / t;
+    s = (s + q - 1) / q * q;
+    for (int64_t r = d; r > 0; r -= s)
+        out.push_back(std::min(s, r));
+    return out;
+}
 
 bool ipmm_supported(int64_t m, int64_t k, int64_t n, int levels) {
     if (m != n || levels < 0)
@@ -726,7 +778,7 @@ bool ipmm_supported(int64_t m, int64_t k, int64_t n, int levels) {
 }
 
 Resolved resolve_schedule(int schedule, int64_t m, int64_t k, int64_t n, bool beta_nonzero,
-                          int levels) {
+                          int levels, int blocks) {
     Resolved r;
     r.levels = levels;
     if (levels < 0 || levels > 24) {
@@ -785,6 +837,16 @@ Resolved resolve_schedule(int schedule, int64_t m, int64_t k, int64_t n, bool be
         if (!square || !divisible)
             shape_error("Table 7 needs m == k == n divisible by 2^levels");
         break;
+    case WS_BLOCKED:
+    case WS_BLOCKED_ACC:
+        r.table = schedule == WS_BLOCKED ? TAB_BLOCKED_HL : TAB_BLOCKED_ACC;
+        if (blocks < 1 || blocks > 64) {
+            r.status = WS_EINVAL;
+            r.error = "the block count t of Section 7.2 must lie in [1, 64]";
+        } else if (schedule == WS_BLOCKED_ACC && (!square || m % blocks)) {
+            shape_error("blocked accumulation over Table 9 needs m == k == n divisible by t");
+        }
+        break;
     default:
         r.status = WS_ESCHEDULE;
         r.error = "unknown schedule";
@@ -816,7 +878,7 @@ void build_plan(const PlanKey &key, Plan &plan) {
         (op.kind == WS_OP_GEMM ? plan.gemm_ops : plan.add_ops) += 1;
 }
 
-int64_t workspace_elems(int table, int64_t m, int64_t k, int64_t n, int levels) {
+int64_t workspace_elems(int table, int64_t m, int64_t k, int64_t n, int levels, int blocks) {
     PlanKey key{};
     key.m = m;
     key.k = k;
@@ -826,9 +888,13 @@ int64_t workspace_elems(int table, int64_t m, int64_t k, int64_t n, int levels) 
     key.ldb = n;
     key.ldc = n;
     key.alpha = 1;
-    key.beta = (table == TAB_HL || table == TAB_ACC || table == TAB_ACLR || table == TAB_ACCR) ? 1 : 0;
+    key.beta = (table == TAB_HL || table == TAB_ACC || table == TAB_ACLR || table == TAB_ACCR ||
+                table == TAB_BLOCKED_HL || table == TAB_BLOCKED_ACC)
+                   ? 1
+                   : 0;
     key.table = table;
     key.levels = levels;
+    key.blocks = (table == TAB_BLOCKED_HL || table == TAB_BLOCKED_ACC) ? blocks : 0;
     std::vector<OpDesc> none;
     Emitter measure(key.p, true, false, none);
     run(measure, key);

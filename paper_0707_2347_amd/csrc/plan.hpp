@@ -31,11 +31,14 @@ enum Table : int {
     TAB_ACCR = 7,   // Table 7
     TAB_ACC = 9,    // Table 9
     TAB_IPMM = 12,  // Algorithm 2
+    TAB_BLOCKED_HL = 13,   // Section 7.2, t x t blocks over Table 2
+    TAB_BLOCKED_ACC = 14,  // Section 7.2, t x t blocks over Table 9
 };
 
 struct PlanKey {
     int64_t m, k, n, p, lda, ldb, ldc, alpha, beta;
     int32_t dtype, table, levels, fuse;
+    int32_t blocks;   // t of the blocked tables, 0 for the others
     bool operator==(const PlanKey &o) const;
 };
 
@@ -58,14 +61,19 @@ struct Resolved {
 };
 
 // Map the public schedule selector and beta to a table, checking shapes.
+// `blocks` is t of the blocked schedules (ignored by the others).
 Resolved resolve_schedule(int schedule, int64_t m, int64_t k, int64_t n, bool beta_nonzero,
-                          int levels);
+                          int levels, int blocks = 2);
 
 // Build the plan for an already resolved request.
 void build_plan(const PlanKey &key, Plan &plan);
 
 // Temporaries (elements) of a resolved table at this shape.
-int64_t workspace_elems(int table, int64_t m, int64_t k, int64_t n, int levels);
+int64_t workspace_elems(int table, int64_t m, int64_t k, int64_t n, int levels, int blocks = 2);
+
+// Lengths of the consecutive parts of one dimension of length d in the
+// blocked accumulation with t blocks per dimension and depth L.
+std::vector<int64_t> block_parts(int64_t d, int t, int L);
 
 bool ipmm_supported(int64_t m, int64_t k, int64_t n, int levels);
 

@@ -21,7 +21,7 @@ def to_host(x):
 
 
 def call(schedule, A, B, C, alpha, beta, p, levels, *, dtype=capi.WS_F64, base=capi.WS_BASE_F64_MFMA,
-         flags=0, workspace=None, workspace_bytes=0):
+         flags=0, workspace=None, workspace_bytes=0, blocks=0):
     """Run one product on cuda:0; return (status, C, A, B) as int64 numpy arrays."""
     t = torch()
     m, k = A.shape
@@ -31,7 +31,7 @@ def call(schedule, A, B, C, alpha, beta, p, levels, *, dtype=capi.WS_F64, base=c
     stream = t.cuda.current_stream()
     args = capi.make_args(m, k, n, p, dA, dB, dC, alpha, beta, schedule, levels, dtype=dtype,
                           base=base, stream=stream, flags=flags, workspace=workspace,
-                          workspace_bytes=workspace_bytes)
+                          workspace_bytes=workspace_bytes, blocks=blocks)
     st = capi.wsmul_mod_p_ex(args)
     t.cuda.synchronize()
     return st, to_host(dC), to_host(dA), to_host(dB)

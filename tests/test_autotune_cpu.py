@@ -24,8 +24,9 @@ PRIMES = [3, 65521, 1048573, 8388593, 16777213]
 
 
 def _choice(m, k, n, p, beta=0, budget=(1 << 64) - 1, schedule=capi.WS_AUTO, levels=-1,
-            base=capi.WS_BASE_AUTO):
-    return capi.wsmul_autotune(m, k, n, p, capi.WS_F64, budget, schedule, levels, base, beta)
+            base=capi.WS_BASE_AUTO, blocks=0):
+    return capi.wsmul_autotune(m, k, n, p, capi.WS_F64, budget, schedule, levels, base, beta,
+                               blocks)[:4]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -74,6 +75,26 @@ def test_fixed_inputs_are_kept():
     assert st == capi.WS_OK and base == capi.WS_BASE_F64_MFMA
 
 
+@pytest.mark.parametrize("n,p,budget", [(16384, 8388593, 512 << 20), (8192, 1048573, 100 << 20)])
+def test_blocked_accumulation_under_small_budget(n, p, budget):
+    """An accumulating product whose unblocked schedules do not fit the budget
+    (Table 9 needs 2(n/2)^2 entries at one level) still gets a Winograd plan:
+    Section 7.2's blocks, with temporaries within the budget."""
+    assert capi.wsmul_workspace_bytes(n, n, n, capi.WS_F64, capi.WS_TWO_TEMP, 1, 1) > budget
+    st, sched, lev, base, t = capi.wsmul_autotune(n, n, n, p, capi.WS_F64, budget, capi.WS_AUTO,
+                                                  -1, capi.WS_BASE_F64_MFMA, 3)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    assert sched in (capi.WS_BLOCKED, capi.WS_BLOCKED_ACC) and lev >= 1 and 2 <= t <= 4
+    info = capi.wsmul_plan_info(capi.make_args(n, n, n, p, beta=3, schedule=sched, levels=lev,
+                                               blocks=t))
+    assert info.workspace_bytes <= budget
+    # a fixed blocked schedule keeps the caller's t
+    st, sched2, lev2, _, t2 = capi.wsmul_autotune(n, n, n, p, capi.WS_F64, budget,
+                                                  capi.WS_BLOCKED_ACC, -1,
+                                                  capi.WS_BASE_F64_MFMA, 3, 4)
+    assert st == capi.WS_OK and sched2 == capi.WS_BLOCKED_ACC and t2 == 4 and lev2 >= 1
+
+
 def test_overwriting_schedules_never_chosen():
     for shape in SHAPES:
         for beta in (0, 1):
@@ -100,7 +121,7 @@ def test_cache_file_round_trip(tmp_path):
     cache = tmp_path / "tune.jsonl"
     code = ("import sys; sys.path.insert(0, %r)\n"
             "from paper_0707_2347_amd import capi\n"
-            "print(capi.wsmul_autotune(3000, 2000, 1000, 1048573)[1:])\n" % ROOT)
+            "print(capi.wsmul_autotune(3000, 2000, 1000, 1048573)[1:4])\n" % ROOT)
     env = dict(os.environ, WSMUL_TUNE_CACHE=str(cache))
     first = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
                            timeout=120)

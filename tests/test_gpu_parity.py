@@ -193,6 +193,51 @@ def test_8192x4096x8192(schedule, levels):
     assert capi.wsmul_get_stats().workspace_bytes == want
 
 
+BLOCKED = [
+    # schedule, shape, levels, t, beta
+    (capi.WS_BLOCKED, (256, 256, 256), 2, 2, 11), (capi.WS_BLOCKED, (384, 384, 384), 2, 3, 11),
+    (capi.WS_BLOCKED, (300, 200, 100), 1, 3, 11), (capi.WS_BLOCKED, (256, 128, 512), 1, 4, 0),
+    (capi.WS_BLOCKED_ACC, (256, 256, 256), 3, 2, 11), (capi.WS_BLOCKED_ACC, (384, 384, 384), 2, 3, 11),
+    (capi.WS_BLOCKED_ACC, (270, 270, 270), 1, 3, 11), (capi.WS_BLOCKED_ACC, (128, 128, 128), 1, 1, 0),
+]
+
+
+@pytest.mark.parametrize("dtype", [capi.WS_F64, capi.WS_I64])
+@pytest.mark.parametrize("schedule,shape,levels,t,beta", BLOCKED)
+def test_blocked_schedules(schedule, shape, levels, t, beta, dtype):
+    """Section 7.2's blocked accumulation (ragged parts and blocks included)."""
+    m, k, n = shape
+    print("blocked", schedule, shape, levels, t, beta, dtype, flush=True)
+    p = 8388593 if levels % 2 else 65521
+    A, B, C = inputs.uniform(m * 13 + k * 7 + n + t, m, k, n, p, with_c=True)
+    st, C2, A2, B2 = call(schedule, A, B, C, 5, beta, p, levels, dtype=dtype, blocks=t)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, 5, beta, p))
+    name = "blocked" if schedule == capi.WS_BLOCKED else "blocked_acc"
+    r = replay(name, A, B, C, 5, beta, p, levels, blocks=t)
+    assert np.array_equal(C2, r.C)
+    assert np.array_equal(A2, A) and np.array_equal(B2, B)
+
+
+@pytest.mark.parametrize("schedule,levels,t,want", [
+    (capi.WS_BLOCKED, 3, 2, 33_030_144), (capi.WS_BLOCKED_ACC, 3, 2, 22_020_096),
+    (capi.WS_BLOCKED, 2, 3, 3 * (684**2 + 342**2) * 8)])
+def test_acc_4096_blocked(schedule, levels, t, want):
+    """The accumulating 4096^3 product under Section 7.2's blocks, with a
+    caller workspace of exactly the reported size (no allocation inside)."""
+    torch = __import__("torch")
+    w = inputs.WORKLOADS["acc_4096_p65521_l3"]
+    A, B, C = inputs.uniform(w["seed"], w["m"], w["k"], w["n"], w["p"], with_c=True)
+    ws = torch.empty(want // 8, dtype=torch.float64, device="cuda:0")
+    st, C2, A2, B2 = call(schedule, A, B, C, 1, 1, w["p"], levels, blocks=t, workspace=ws,
+                          workspace_bytes=want)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    _sampled(A, B, C, 1, 1, w["p"], C2)
+    s = capi.wsmul_get_stats()
+    assert s.workspace_bytes == want and s.internal_alloc_bytes == 0
+    assert np.array_equal(A2, A) and np.array_equal(B2, B)
+
+
 def test_attached_workspace_exact_size_and_no_hidden_allocation():
     t = __import__("torch")
     p = 65521

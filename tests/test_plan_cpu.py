@@ -40,10 +40,12 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
-def _interp(schedule, m, k, n, p, alpha, beta, levels, seed, fuse=True, dtype=capi.WS_F64):
+def _interp(schedule, m, k, n, p, alpha, beta, levels, seed, fuse=True, dtype=capi.WS_F64,
+            blocks=0):
     A, B, C = inputs.uniform(seed, m, k, n, p, with_c=True)
     args = capi.make_args(m, k, n, p, alpha=alpha, beta=beta, schedule=schedule,
-                          levels=levels, dtype=dtype, flags=0 if fuse else capi.WS_FLAG_NOFUSE)
+                          levels=levels, dtype=dtype, flags=0 if fuse else capi.WS_FLAG_NOFUSE,
+                          blocks=blocks)
     info = capi.wsmul_plan_info(args)
     ops = capi.wsmul_plan_export(args)
     rng = np.random.default_rng(seed + 1)
@@ -89,6 +91,63 @@ def test_plan_reproduces_oracle(schedule, shape, levels, acc, fuse):
     rs = replay_shape(name, m, k, n, p, levels, beta_nonzero=bool(beta))
     assert info.workspace_bytes == 8 * rs.peak
     assert info.element_additions == rs.adds
+
+
+BLOCKED = [
+    # schedule, shape, levels, t (0 = the default 2), beta
+    (capi.WS_BLOCKED, (64, 64, 64), 2, 0, 7), (capi.WS_BLOCKED, (96, 96, 96), 1, 3, 7),
+    (capi.WS_BLOCKED, (64, 32, 128), 2, 2, 7), (capi.WS_BLOCKED, (37, 50, 29), 1, 3, 7),
+    (capi.WS_BLOCKED, (100, 100, 100), 2, 3, 0), (capi.WS_BLOCKED, (33, 17, 65), 2, 4, 7),
+    (capi.WS_BLOCKED, (32, 32, 32), 2, 1, 7), (capi.WS_BLOCKED, (5, 70, 3), 1, 3, 7),
+    (capi.WS_BLOCKED_ACC, (64, 64, 64), 2, 2, 7), (capi.WS_BLOCKED_ACC, (96, 96, 96), 2, 3, 7),
+    (capi.WS_BLOCKED_ACC, (90, 90, 90), 2, 3, 7), (capi.WS_BLOCKED_ACC, (64, 64, 64), 1, 4, 0),
+]
+
+
+@pytest.mark.parametrize("fuse", [True, False])
+@pytest.mark.parametrize("schedule,shape,levels,t,beta", BLOCKED)
+def test_blocked_plan_reproduces_oracle(schedule, shape, levels, t, beta, fuse):
+    """Section 7.2's blocked accumulation: the plan's value, its temporaries
+    (one block call's) and its addition count equal the oracle's replay."""
+    m, k, n = shape
+    p = 8388593 if levels % 2 else 65521
+    alpha = 5
+    (A, B, C), (A2, B2, C2), info = _interp(schedule, m, k, n, p, alpha, beta, levels,
+                                             seed=m * 5 + k + n * 3 + t, fuse=fuse, blocks=t)
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, alpha, beta, p))
+    assert np.array_equal(A2, A) and np.array_equal(B2, B)
+    name = "blocked" if schedule == capi.WS_BLOCKED else "blocked_acc"
+    rs = replay_shape(name, m, k, n, p, levels, beta_nonzero=True, blocks=t or 2)
+    assert info.workspace_bytes == 8 * rs.peak
+    assert info.element_additions == rs.adds
+    assert capi.wsmul_schedule_name(info.schedule).startswith("section7.2-blocked")
+
+
+def test_blocked_workload_bytes():
+    """The accumulating 4096^3 product with three levels: t = 2 needs a
+    quarter (Table 2) or a sixth (Table 9) of n^2 entries at most."""
+    info = lambda s, t: capi.wsmul_plan_info(capi.make_args(
+        4096, 4096, 4096, 65521, beta=1, schedule=s, levels=3, blocks=t)).workspace_bytes
+    assert info(capi.WS_BLOCKED, 2) == 33_030_144 < 4096 * 4096 * 8 // 4
+    assert info(capi.WS_BLOCKED_ACC, 2) == 22_020_096 < 4096 * 4096 * 8 // 6
+    assert info(capi.WS_BLOCKED, 3) == 14_737_464
+    assert info(capi.WS_BLOCKED_ACC, 4) == 2 * (512**2 + 256**2 + 128**2) * 8
+    wb = capi.wsmul_workspace_bytes
+    assert wb(4096, 4096, 4096, capi.WS_F64, capi.WS_BLOCKED, 3, 1) == 33_030_144
+
+
+def test_blocked_argument_errors():
+    a = capi.make_args(12, 12, 12, 65521, A=16, B=16, C=16, beta=1, schedule=capi.WS_BLOCKED,
+                       levels=1, blocks=65)
+    import ctypes
+    s = capi.ws_stats()
+    assert capi.lib().wsmul_plan_info(ctypes.byref(a), ctypes.byref(s)) == capi.WS_EINVAL
+    a.schedule, a.blocks = capi.WS_BLOCKED_ACC, 5                  # 12 not divisible by 5
+    assert capi.lib().wsmul_plan_info(ctypes.byref(a), ctypes.byref(s)) == capi.WS_ESHAPE
+    a.k, a.blocks = 8, 2                                           # not square
+    assert capi.lib().wsmul_plan_info(ctypes.byref(a), ctypes.byref(s)) == capi.WS_ESHAPE
+    a.schedule = capi.WS_BLOCKED                                   # Table 2 takes any shape
+    assert capi.lib().wsmul_plan_info(ctypes.byref(a), ctypes.byref(s)) == capi.WS_OK
 
 
 def test_fusion_reduces_launches():
