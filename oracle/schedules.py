@@ -51,6 +51,20 @@ Readings of the paper taken here (where it is silent or garbled):
   A_il B_lj for l = 1..t in order, the first with beta and the others with 1,
   each by one call of the base schedule (Table 2, or Table 9 for square
   blocks).  Only one call's temporaries exist at a time.
+* Table 8's X holds a T block (k/2 x n/2) and then products (m/2 x n/2), so it
+  is max(m/2, k/2) x n/2; Y holds S blocks (m/2 x k/2).  Its two plain
+  products (rows 12 and 22) are Table 1 calls.
+* Algorithm 1 (IP0vMM) as its section describes it, with the loop bounds and
+  the accumulation read as C_i <- A_ij B_j + C_i (the printed indices are
+  garbled): n = min(m, k, n) must divide m and k, and A, B, C are cut into
+  n x n squares A_ij (m0 x k0 of them), B_j and C_i.  With m0 >= 2: C_1 by
+  Table 1 with its temporaries in C_2, then A_11 is free space; C_i for
+  i >= 2 by Table 4 (overwriting A_i1) and then C_i += A_ij B_j for j >= 2
+  by Table 2, all with temporaries in A_11.  With m0 = 1 (m = n <= k, the
+  shapes the paper times): C by Table 3 from A_1 and B_1, then C += A_j B_j
+  by Table 6 with temporaries in the freed A_1.  Temporaries in a free
+  square are laid out as in Algorithm 2 (quadrants, recursion in the
+  bottom-right one).
 * Algorithm 2 with the depth parameter L: at depth d < L the three quadrant
   products are Winograd calls of depth L - d, with inner dimension cut in
   chunks of K = min(s/2, k); at depth L the remaining corner is a classical
@@ -64,8 +78,9 @@ from contextlib import contextmanager
 import numpy as np
 
 SCHEDULES = ("classical", "t1", "hl", "ip", "ovr", "aclr", "accr", "acc", "ipmm",
-             "blocked", "blocked_acc")
-OVERWRITES = {"ip": "AB", "ovr": "B", "aclr": "AB", "accr": "B"}
+             "blocked", "blocked_acc", "ovl", "acr", "ip0vmm")
+OVERWRITES = {"ip": "AB", "ovr": "B", "aclr": "AB", "accr": "B", "ovl": "A", "acr": "B",
+              "ip0vmm": "AB"}
 
 
 def quads(M):
@@ -298,6 +313,43 @@ class Winograd:
         self.add(C12, C12, A12)                  # 22 U5 = U4 + P3
         self.destroy(A, B)
 
+    # --------------------------------------------------------- Table 4 (OvL)
+    def ovl(self, A, B, C, a, lev):
+        """Table 4: C <- a*A*B with one temporary X ((n/2)^2); overwrites A."""
+        self.calls["ovl"] += 1
+        if lev == 0:
+            self.leaf(A, B, C, a, 0, False)
+            self.destroy(A)
+            return
+        n = C.shape[0]
+        A11, A12, A21, A22 = quads(A)
+        B11, B12, B21, B22 = quads(B)
+        C11, C12, C21, C22 = quads(C)
+        with self.frame((n // 2, n // 2)) as (X,):
+            self.sub(C22, A11, A21)              # 1  S3
+            self.add(A21, A21, A22)              # 2  S1
+            self.sub(C12, A21, A11)              # 3  S2 = S1 - A11
+            self.sub(C21, B12, B11)              # 4  T1
+            self.ovl(A11, B11, C11, a, lev - 1)  # 5  P1
+            self.sub(A11, B22, B12)              # 6  T3
+            self.ip(C22, A11, X, a, lev - 1)     # 7  P7 = S3 T3
+            self.sub(A11, B22, C21)              # 8  T2 = B22 - T1
+            self.ip(A21, C21, C22, a, lev - 1)   # 9  P5 = S1 T1
+            self.sub(C21, A12, C12)              # 10 S4 = A12 - S2
+            self.ovl(C21, B22, A21, a, lev - 1)  # 11 P3 = S4 B22
+            self.ovl(C12, A11, C21, a, lev - 1)  # 12 P6 = S2 T2
+            self.sub(A11, A11, B21)              # 13 T4 = T2 - B21
+            self.add(C21, C11, C21)              # 14 U2 = P1 + P6
+            self.add(C12, C21, C22)              # 15 U4 = U2 + P5
+            self.add(C21, C21, X)                # 16 U3 = U2 + P7
+            self.add(C22, C21, C22)              # 17 U7 = U3 + P5
+            self.add(C12, C12, A21)              # 18 U5 = U4 + P3
+            self.ovl(A12, B21, X, a, lev - 1)    # 19 P2
+            self.add(C11, C11, X)                # 20 U1 = P1 + P2
+            self.ip(A22, A11, A21, a, lev - 1)   # 21 P4 = A22 T4
+            self.sub(C21, C21, A21)              # 22 U6 = U3 - P4
+        self.destroy(A)
+
     # --------------------------------------------------------- Table 5 (OvR)
     def ovr(self, A, B, C, a, lev):
         """Table 5: C <- a*A*B with one temporary X ((n/2)^2); overwrites B."""
@@ -415,6 +467,49 @@ class Winograd:
             self.add(C12, B21, C12)                  # 24 U5 = U4 + P3
         self.destroy(B)
 
+    # --------------------------------------------------------- Table 8 (AcR)
+    def acr(self, A, B, C, a, b, lev):
+        """Table 8: C <- a*A*B + b*C for any even shape with two temporaries,
+        X (max(m/2, k/2) x n/2) and Y (m/2 x k/2); overwrites B only; five
+        accumulating calls and two Table 1 calls."""
+        self.calls["acr"] += 1
+        if lev == 0:
+            self.leaf(A, B, C, a, b, True)
+            self.destroy(B)
+            return
+        m, k = A.shape
+        n = B.shape[1]
+        h, kk, w = m // 2, k // 2, n // 2
+        A11, A12, A21, A22 = quads(A)
+        B11, B12, B21, B22 = quads(B)
+        C11, C12, C21, C22 = quads(C)
+        with self.frame((max(h, kk), w), (h, kk)) as (X, Y):
+            XT, XP = X[:kk], X[:h]                   # X holding a T block, then a product
+            self.sub(C22, C22, C12)                  # 1  Z1
+            self.sub(XT, B12, B11)                   # 2  T1
+            self.sub(C21, C21, C22)                  # 3  Z2 = C21 - Z1
+            self.sub(B12, B22, B12)                  # 4  T3
+            self.sub(Y, A11, A21)                    # 5  S3
+            self.acr(Y, B12, C22, a, b, lev - 1)     # 6  P7 + b Z1
+            self.add(Y, A21, A22)                    # 7  S1
+            self.sub(B12, B22, XT)                   # 8  T2 = B22 - T1
+            self.acr(Y, XT, C12, a, b, lev - 1)      # 9  P5 + b C12
+            self.sub(XT, B12, B21)                   # 10 T4 = T2 - B21
+            self.acr(A22, XT, C21, a, -b, lev - 1)   # 11 P4 - b Z2
+            self.t1(A11, B11, XP, a, lev - 1)        # 12 P1
+            self.acr(A12, B21, C11, a, b, lev - 1)   # 13 P2 + b C11
+            self.add(C11, XP, C11)                   # 14 U1 = P1 + P2
+            self.sub(Y, Y, A11)                      # 15 S2 = S1 - A11
+            self.acr(Y, B12, XP, a, 1, lev - 1)      # 16 U2 = a S2 T2 + P1
+            self.add(C22, XP, C22)                   # 17 U3 = U2 + P7
+            self.sub(C21, C22, C21)                  # 18 U6 = U3 - P4
+            self.add(C22, C22, C12)                  # 19 U7 = U3 + P5
+            self.add(XP, XP, C12)                    # 20 U4 = U2 + P5
+            self.sub(Y, A12, Y)                      # 21 S4 = A12 - S2
+            self.t1(Y, B22, C12, a, lev - 1)         # 22 P3 = S4 B22
+            self.add(C12, XP, C12)                   # 23 U5 = U4 + P3
+        self.destroy(B)
+
     # --------------------------------------------------------- Table 9 (Acc)
     def acc(self, A, B, C, a, b, lev):
         """Table 9: C <- a*A*B + b*C with two temporaries ((n/2)^2 each);
@@ -489,6 +584,43 @@ class Winograd:
         finally:
             self._regions.pop()
         self.ipmm(A2, B2, C22, a, L, d + 1)
+
+    # ------------------------------------------------------ Algorithm 1 (IP0vMM)
+    def ip0vmm(self, A, B, C, a, lev):
+        """Algorithm 1 and the cutting into squares around it: C <- a*A*B with
+        no extra memory, n = min(m, k, n) dividing m and k.  Overwrites A (and
+        B when m = n); temporaries live in C_2 and then in the freed A_11."""
+        self.calls["ip0vmm"] += 1
+        m, k = A.shape
+        s = B.shape[1]
+        m0, k0 = m // s, k // s
+        Ab = lambda i, j: A[i * s:(i + 1) * s, j * s:(j + 1) * s]
+        Bb = lambda j: B[j * s:(j + 1) * s]
+        Cb = lambda i: C[i * s:(i + 1) * s]
+        if m0 == 1:
+            self.ip(Ab(0, 0), Bb(0), Cb(0), a, lev)
+            self._regions.append(Ab(0, 0))
+            try:
+                for j in range(1, k0):
+                    self.aclr(Ab(0, j), Bb(j), Cb(0), a, 1, lev)
+            finally:
+                self._regions.pop()
+            return
+        self._regions.append(Cb(1))
+        try:
+            self.t1(Ab(0, 0), Bb(0), Cb(0), a, lev)
+        finally:
+            self._regions.pop()
+        self.destroy(Ab(0, 0))
+        self._regions.append(Ab(0, 0))
+        try:
+            for i in range(1, m0):
+                self.ovl(Ab(i, 0), Bb(0), Cb(i), a, lev)
+            for j in range(1, k0):
+                for i in range(m0):
+                    self.hl(Ab(i, j), Bb(j), Cb(i), a, 1, lev)
+        finally:
+            self._regions.pop()
 
     # --------------------------------------- Section 7.2 (blocked accumulation)
     def blocked(self, core, A, B, C, a, b, t, L):
@@ -570,6 +702,11 @@ def _offsets(parts):
     return out
 
 
+def ip0vmm_shape_ok(m, k, n, L):
+    """Shapes Algorithm 1 (with the cutting into n x n squares) runs at depth L."""
+    return n > 0 and n <= min(m, k) and m % n == 0 and k % n == 0 and n % (2 ** L) == 0
+
+
 def ipmm_shape_ok(m, k, n, L):
     """Shapes Algorithm 2 can run with depth L under the chunking above."""
     if m != n or L < 0:
@@ -604,6 +741,15 @@ def _check(schedule, m, k, n, p, beta, L, t=2):
         raise ValueError("schedule acc needs a square shape")
     if schedule == "ipmm" and not ipmm_shape_ok(m, k, n, L):
         raise ValueError("shape not supported by ipmm at this depth")
+    if beta % p and schedule in ("ovl", "ip0vmm"):
+        raise ValueError("schedule %s computes C = A*B only (beta must be 0)" % schedule)
+    if schedule == "ovl" and (not (m == k == n) or m % (2 ** L)):
+        raise ValueError("schedule ovl needs a square shape divisible by 2**levels")
+    if schedule == "acr" and (m % (2 ** L) or k % (2 ** L) or n % (2 ** L)):
+        raise ValueError("schedule acr needs every dimension divisible by 2**levels")
+    if schedule == "ip0vmm" and not ip0vmm_shape_ok(m, k, n, L):
+        raise ValueError("schedule ip0vmm needs n = min(m, k, n) dividing m and k, "
+                         "and divisible by 2**levels")
 
 
 def _run(w, schedule, A, B, C, a, b, L, t=2):
@@ -628,6 +774,12 @@ def _run(w, schedule, A, B, C, a, b, L, t=2):
         w.accr(A, B, C, a, b, L)
     elif schedule == "ipmm":
         w.ipmm(A, B, C, a, L)
+    elif schedule == "ovl":
+        w.ovl(A, B, C, a, L)
+    elif schedule == "acr":
+        w.acr(A, B, C, a, b, L)
+    elif schedule == "ip0vmm":
+        w.ip0vmm(A, B, C, a, L)
     elif schedule == "blocked":
         w.blocked(w.hl, A, B, C, a, b, t, L)
     elif schedule == "blocked_acc":

@@ -355,3 +355,102 @@ def test_blocked_workload_bytes():
     # parts 1368, 1368, 1360: the temporaries of the largest block
     assert b("blocked", 3) == 3 * (684**2 + 342**2 + 171**2) * 8 == 14_737_464
     assert b("acc", 2) == 88_080_384
+
+
+# ------------------------------ the rectangular overwrite family (Section 5.3)
+def W8r(m, k, n, l):
+    """Table 8: five accumulating calls, two Table 1 calls, 16 additions
+    (8 on C-sized blocks, 4 on S blocks, 4 on T blocks)."""
+    if l == 0:
+        return 2 * m * n * k
+    h, kk, w = m // 2, k // 2, n // 2
+    return (5 * W8r(h, kk, w, l - 1) + 2 * W1r(h, kk, w, l - 1) + 4 * h * kk + 4 * kk * w
+            + 8 * h * w)
+
+
+def E1r(m, k, n, l):
+    """Eq. (1) summed to depth l."""
+    if l == 0:
+        return 0
+    h, kk, w = m // 2, k // 2, n // 2
+    return h * max(kk, w) + kk * w + E1r(h, kk, w, l - 1)
+
+
+def E8r(m, k, n, l):
+    """Section 5.3's extra memory of Table 8: X = max(m/2, k/2) n/2, Y = m/2 k/2,
+    plus the larger of its callees (Table 8 or Table 1) one level down."""
+    if l == 0:
+        return 0
+    h, kk, w = m // 2, k // 2, n // 2
+    return max(h, kk) * w + h * kk + max(E8r(h, kk, w, l - 1), E1r(h, kk, w, l - 1))
+
+
+@pytest.mark.parametrize("n,l", [(n, l) for n in (2, 8, 32) for l in range(0, n.bit_length())])
+def test_ovl_arithmetic_and_memory(n, l):
+    """Table 4 performs Table 1's arithmetic (7 products, 15 additions) with
+    one (n/2)^2 temporary per level: M(n) = (n/2)^2 + M(n/2) -> n^2/3."""
+    r = replay_shape("ovl", n, n, n, levels=l)
+    assert r.ops == W1(n, l)
+    assert r.peak == sum_quarters(n * n, l)
+
+
+@pytest.mark.parametrize("e", range(1, 7))
+def test_ovl_closed_forms(e):
+    """At full recursion: 6n^log7 - 5n^2 operations, at most n^2/3 extra
+    memory, and A(n) = (n/2)^2 + 4A(n/2) = n^2 log2(n) / 4 allocations."""
+    n = 2**e
+    r = replay_shape("ovl", n, n, n, levels=e)
+    assert r.ops == 6 * 7**e - 5 * 4**e
+    assert r.peak == Fraction(n * n, 3) * (1 - Fraction(1, 4**e)) < Fraction(n * n, 3)
+    assert r.allocated == Fraction(n * n * e, 4)
+
+
+@pytest.mark.parametrize("shape,l", [((32, 32, 32), 3), ((64, 32, 128), 2), ((128, 64, 32), 3),
+                                     ((32, 128, 64), 2), ((16, 64, 32), 4), ((64, 16, 16), 2)])
+def test_acr_arithmetic_and_memory(shape, l):
+    m, k, n = shape
+    r = replay_shape("acr", m, k, n, levels=l, beta_nonzero=True)
+    assert r.ops == W8r(m, k, n, l)
+    assert r.peak == E8r(m, k, n, l)
+
+
+@pytest.mark.parametrize("e", range(1, 7))
+def test_acr_square_closed_forms(e):
+    """Square Table 8 at full recursion: W(n) = 5W(n/2) + 2W1(n/2) + 16(n/2)^2
+    gives 6n^log7 + 2n^log5 - 6n^2; its extra memory stays within 2n^2/3."""
+    n = 2**e
+    r = replay_shape("acr", n, n, n, levels=e, beta_nonzero=True)
+    assert r.ops == 6 * 7**e + 2 * 5**e - 6 * 4**e
+    assert r.peak <= Fraction(2 * n * n, 3)
+
+
+@pytest.mark.parametrize("shape", [(16, 32, 64), (32, 16, 64), (64, 32, 16), (64, 64, 16),
+                                   (16, 64, 32), (32, 64, 16)])
+def test_acr_rectangular_memory_bounds(shape):
+    """Section 5.3: if m < k < n or k < m < n Table 8 needs less than Table 1;
+    otherwise it needs less than (max(m, k) n + m k) / 3."""
+    m, k, n = shape
+    l = min(shape).bit_length() - 1
+    e8 = replay_shape("acr", m, k, n, levels=l, beta_nonzero=True).peak
+    if (m < k < n) or (k < m < n):
+        assert e8 < replay_shape("t1", m, k, n, levels=l).peak
+    else:
+        assert e8 < Fraction(max(m, k) * n + m * k, 3)
+
+
+@pytest.mark.parametrize("shape,l", [((64, 128, 32), 2), ((96, 64, 32), 1), ((32, 96, 32), 3),
+                                     ((64, 32, 32), 2), ((32, 32, 32), 5), ((128, 256, 64), 6)])
+def test_ip0vmm_arithmetic_and_no_memory(shape, l):
+    """Algorithm 1 allocates nothing; its operations are those of its calls:
+    m0 Table 1/4 products and m0 (k0 - 1) Table 2 accumulations of n x n
+    squares, or (m0 = 1) one Table 3 product and k0 - 1 Table 6 ones."""
+    m, k, n = shape
+    r = replay_shape("ip0vmm", m, k, n, levels=l)
+    assert r.peak == 0 and r.allocated == 0
+    m0, k0 = m // n, k // n
+    if m0 == 1:
+        assert r.ops == W1(n, l) + (k0 - 1) * W6(n, l)
+    else:
+        assert r.ops == m0 * W1(n, l) + m0 * (k0 - 1) * W2(n, l)
+    if l == n.bit_length() - 1 and m0 > 1:                      # full recursion
+        assert r.ops == m0 * (6 * 7**l - 5 * 4**l) + m0 * (k0 - 1) * (6 * 7**l - 4 * 4**l)

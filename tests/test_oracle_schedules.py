@@ -290,3 +290,134 @@ def test_blocked_rejects_bad_blocks():
     A2, B2, C2 = inputs.uniform(24, 12, 8, 12, P, True)
     with pytest.raises(ValueError):
         replay("blocked_acc", A2, B2, C2, 1, 1, P, 1, blocks=2)  # not square
+
+
+# ------------------------------ the rectangular overwrite family (Section 5.3)
+OVERWRITE_FAMILY = [
+    # schedule, shape, levels, accumulates
+    ("ovl", (32, 32, 32), 1, False), ("ovl", (64, 64, 64), 3, False),
+    ("ovl", (16, 16, 16), 4, False),
+    ("acr", (32, 32, 32), 2, True), ("acr", (64, 32, 128), 2, True),
+    ("acr", (128, 64, 32), 3, True), ("acr", (32, 128, 64), 2, True),
+    ("acr", (48, 16, 80), 1, True),
+    ("ip0vmm", (64, 128, 32), 2, False), ("ip0vmm", (96, 64, 32), 1, False),
+    ("ip0vmm", (32, 96, 32), 3, False), ("ip0vmm", (64, 32, 32), 2, False),
+    ("ip0vmm", (32, 32, 32), 2, False), ("ip0vmm", (128, 128, 64), 2, False),
+]
+
+
+@pytest.mark.parametrize("p", [P, 8388593])
+@pytest.mark.parametrize("schedule,shape,levels,accumulates", OVERWRITE_FAMILY)
+def test_overwrite_family_value_with_garbage(schedule, shape, levels, accumulates, p):
+    m, k, n = shape
+    A, B, C = inputs.uniform(zlib.crc32(repr((schedule, shape, levels)).encode()), m, k, n, p, True)
+    for seed, (alpha, beta) in enumerate([(1, 1), (3, p - 2), (p - 1, 5), (7, 0)]):
+        if not accumulates:
+            beta = 0
+        r = replay(schedule, A, B, C, alpha, beta, p, levels, garbage_seed=seed)
+        assert np.array_equal(r.C, o1(A, B, C, alpha, beta, p)), (alpha, beta)
+        if schedule == "acr":
+            assert np.array_equal(r.A, A)                      # Table 8 overwrites B only
+        if schedule == "ovl":
+            assert np.array_equal(r.B, B)                      # Table 4 overwrites A only
+        if schedule == "ip0vmm" and m > n:
+            assert np.array_equal(r.B, B)                      # Tables 1, 4, 2 leave B
+
+
+def test_ovl_final_inputs_one_level():
+    """Table 4 at one level ends with A = [[T4, A12], [P4, A22]] and B intact."""
+    n, a = 32, 6
+    A, B, _ = inputs.uniform(25, n, n, n, P)
+    r = replay("ovl", A, B, None, a, 0, P, 1)
+    d = _sp(A, B, np.zeros((n, n), np.int64), a, 0, P)
+    t4 = (d["T2"] - d["B21"]) % P
+    for got, want in zip(_blocks(r.A), [t4, d["A12"], d["P"][4], d["A22"]]):
+        assert np.array_equal(got, want)
+    assert np.array_equal(r.B, B)
+
+
+def test_acr_final_inputs_one_level():
+    """Table 8 at one level ends with B = [[B11, T2], [B21, B22]] and A intact."""
+    n, a, b = 32, 4, 10
+    A, B, C = inputs.uniform(26, n, n, n, P, True)
+    r = replay("acr", A, B, C, a, b, P, 1)
+    d = _sp(A, B, C, a, b, P)
+    for got, want in zip(_blocks(r.B), [d["B11"], d["T2"], d["B21"], d["B22"]]):
+        assert np.array_equal(got, want)
+    assert np.array_equal(r.A, A)
+
+
+def test_ip0vmm_final_state_is_deterministic():
+    for shape in [(64, 128, 32), (32, 96, 32)]:
+        m, k, n = shape
+        A, B, _ = inputs.uniform(27, m, k, n, P)
+        r1 = replay("ip0vmm", A, B, None, 2, 0, P, 2)
+        r2 = replay("ip0vmm", A, B, None, 2, 0, P, 2)
+        assert np.array_equal(r1.A, r2.A) and np.array_equal(r1.B, r2.B)
+
+
+class _OvlReadsDeadA11(Winograd):
+    """Table 4 with rows 3 and 5 exchanged: S2 = S1 - A11 is formed after P1
+    has been allowed to destroy A11."""
+
+    def ovl(self, A, B, C, a, lev):
+        if lev == 0:
+            self.leaf(A, B, C, a, 0, False)
+            self.destroy(A)
+            return
+        n = C.shape[0]
+        A11, A12, A21, A22 = quads(A)
+        B11, B12, B21, B22 = quads(B)
+        C11, C12, C21, C22 = quads(C)
+        with self.frame((n // 2, n // 2)) as (X,):
+            self.sub(C22, A11, A21)
+            self.add(A21, A21, A22)
+            self.sub(C21, B12, B11)
+            self.ovl(A11, B11, C11, a, lev - 1)       # row 5 moved up
+            self.sub(C12, A21, A11)                   # row 3 now reads a dead A11
+            self.sub(A11, B22, B12)
+            self.ip(C22, A11, X, a, lev - 1)
+            self.sub(A11, B22, C21)
+            self.ip(A21, C21, C22, a, lev - 1)
+            self.sub(C21, A12, C12)
+            self.ovl(C21, B22, A21, a, lev - 1)
+            self.ovl(C12, A11, C21, a, lev - 1)
+            self.sub(A11, A11, B21)
+            self.add(C21, C11, C21)
+            self.add(C12, C21, C22)
+            self.add(C21, C21, X)
+            self.add(C22, C21, C22)
+            self.add(C12, C12, A21)
+            self.ovl(A12, B21, X, a, lev - 1)
+            self.add(C11, C11, X)
+            self.ip(A22, A11, A21, a, lev - 1)
+            self.sub(C21, C21, A21)
+        self.destroy(A)
+
+
+def test_garbage_mode_catches_a_planted_mistake_in_table4():
+    n = 32
+    A, B, _ = inputs.uniform(28, n, n, n, P)
+    want = o1(A, B, None, 1, 0, P)
+    w = _OvlReadsDeadA11(P, garbage_seed=0)
+    C = np.zeros((n, n), np.int64)
+    w.ovl(A.copy(), B.copy(), C, 1, 1)
+    assert not np.array_equal(C, want)
+    w = Winograd(P, garbage_seed=0)
+    C = np.zeros((n, n), np.int64)
+    w.ovl(A.copy(), B.copy(), C, 1, 1)
+    assert np.array_equal(C, want)
+
+
+def test_overwrite_family_rejects_unsupported_shapes():
+    A, B, C = inputs.uniform(29, 24, 24, 24, P, True)
+    with pytest.raises(ValueError):
+        replay("ovl", A, B, C, 1, 1, P, 1)            # Table 4 has no beta
+    with pytest.raises(ValueError):
+        replay("acr", A, B, C, 1, 1, P, 4)            # 24 not divisible by 16
+    A2, B2, C2 = inputs.uniform(30, 48, 32, 32, P, True)
+    with pytest.raises(ValueError):
+        replay("ip0vmm", A2, B2, None, 1, 0, P, 1)    # n = 32 does not divide m = 48
+    A3, B3, _ = inputs.uniform(31, 32, 64, 64, P)
+    with pytest.raises(ValueError):
+        replay("ip0vmm", A3, B3, None, 1, 0, P, 1)    # n is not the smallest dimension
