@@ -15,6 +15,12 @@ product.
   t1_16384_p1048573             C = A*B mod 1048573, 16384^3, schedule, depth and base
                                 chosen by the autotuner, against the binary64 and 8-bit
                                 digit bases under fixed schedules
+  overwrite_8192x16384x8192_p8388593
+                                C = A*B mod 8388593 on the largest shape the paper times,
+                                Algorithm 1 (here Table 3, then Table 6 in the freed block:
+                                no workspace, A and B overwritten and restored from copies
+                                outside the timed window), one level, against classical,
+                                Table 1 and Algorithm 2
   acc_4096_p65521_blocked       the default product under Section 7.2's blocked accumulation:
                                 C in t x t blocks (--blocks, default 2), each block by t
                                 Table 9 calls of two levels, extra memory below 2(n/t)^2/3;
@@ -51,7 +57,8 @@ SCHEDULE_NAMES = {0: "classical", 1: "two temporaries (Table 1 / Table 9)",
                   8: "blocked accumulation over Table 2 (Section 7.2)",
                   9: "blocked accumulation over Table 9 (Section 7.2)"}
 WORKLOADS = ("acc_4096_p65521_l3", "t1_512_p65521_l1_i64", "ipmm_8192x4096x8192_p8388593",
-             "t1_16384_p1048573", "acc_4096_p65521_blocked", "batch_2000")
+             "t1_16384_p1048573", "overwrite_8192x16384x8192_p8388593", "acc_4096_p65521_blocked",
+             "batch_2000")
 INPUTS_OF = {"acc_4096_p65521_blocked": "acc_4096_p65521_l3"}   # same product, other schedule
 
 
@@ -252,6 +259,12 @@ def single_product(ctx, name):
         config = {"workload": name, "m": m, "k": k, "n": n, "p": p, "op": "C <- A*B + C",
                   "schedule": label, "levels": lev, "base": "f64 matrix cores",
                   "parallelism": "single GPU"}
+    elif name == "overwrite_8192x16384x8192_p8388593":
+        sched, lev, base = capi.WS_OVERWRITE, lev_or(1), capi.WS_BASE_F64_MFMA
+        config = {"workload": name, "m": m, "k": k, "n": n, "p": p, "op": "C = A*B",
+                  "schedule": "algorithm1-in-place-overwrite-rectangular", "levels": lev,
+                  "base": "f64 matrix cores", "inputs": "A and B restored from copies "
+                  "before each step, outside the timed window", "parallelism": "single GPU"}
     elif name == "acc_4096_p65521_blocked":
         sched, lev, base, blocks = capi.WS_BLOCKED_ACC, lev_or(2), capi.WS_BASE_F64_MFMA, \
             a.blocks
@@ -283,7 +296,21 @@ def single_product(ctx, name):
     head = mkargs(sched, lev, base, ws, nbytes, blocks)
     steps, warmup = a.steps, a.warmup
     log("timing %d steps (%s, %d levels)" % (steps, config["schedule"], lev))
-    ms_step = ctx.timed(lambda: run(head), steps, warmup)
+    overwrites = sched in (capi.WS_OVERWRITE, capi.WS_OVR, capi.WS_ACCR, capi.WS_OVL,
+                           capi.WS_ACR)
+    if overwrites:
+        # each step starts from the pristine inputs; the copies are not timed
+        A0, B0 = dA.clone(), dB.clone()
+
+        def restore():
+            dA.copy_(A0)
+            dB.copy_(B0)
+        for _ in range(warmup):
+            restore()
+            run(head)
+        ms_step = ctx.event_ms(lambda: run(head), steps, restore)
+    else:
+        ms_step = ctx.timed(lambda: run(head), steps, warmup)
     stats = capi.wsmul_get_stats()
     value = flops / (ms_step * 1e-3) / 1e9
     log("%s: %.3f ms/step, %.1f Gop/s, temporaries %d B" % (name, ms_step, value,
@@ -322,6 +349,10 @@ def single_product(ctx, name):
             compare("overwrite_table6", capi.WS_OVERWRITE, lev, restore=True)
         elif name == "ipmm_8192x4096x8192_p8388593":
             compare("two_temporaries_table1", capi.WS_TWO_TEMP, 1)
+        elif name == "overwrite_8192x16384x8192_p8388593":
+            compare("algorithm1_2_levels", capi.WS_OVERWRITE, 2, restore=True)
+            compare("table1_1_level", capi.WS_TWO_TEMP, 1)
+            compare("algorithm2_1_level", capi.WS_READONLY_INPLACE, 1)
         elif name == "acc_4096_p65521_blocked":
             compare("table9_unblocked_3_levels", capi.WS_TWO_TEMP, 3)
             compare("blocked_t2_table2_2_levels", capi.WS_BLOCKED, 2, blocks=2)
@@ -417,8 +448,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--levels", type=int, default=None,
-                    help="Winograd levels of the accumulating 4096^3 workloads "
-                         "(default 3 unblocked, 2 blocked)")
+                    help="Winograd levels of the 4096^3 accumulation (default 3; 2 when "
+                         "blocked) and of the Algorithm 1 workload (default 1)")
     ap.add_argument("--blocks", type=int, default=2,
                     help="t of the blocked accumulation workload")
     ap.add_argument("--workload", default=WORKLOADS[0], choices=WORKLOADS)

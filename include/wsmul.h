@@ -64,15 +64,31 @@ typedef enum {
 typedef enum {
     WS_CLASSICAL = 0,        /* no Winograd level: one base product (comparator)    */
     WS_TWO_TEMP = 1,         /* beta == 0: Table 1; beta != 0: Table 9 (square)    */
-    WS_OVERWRITE = 2,        /* beta == 0: Table 3; beta != 0: Table 6; destroys A, B */
+    WS_OVERWRITE = 2,        /* square: Table 3 (beta == 0) or Table 6; otherwise
+                                Algorithm 1 (beta == 0) or Table 8; destroys A and/or B */
     WS_READONLY_INPLACE = 3, /* Algorithm 2; beta must be 0; no temporary at all   */
     WS_HL_THREE_TEMP = 4,    /* Table 2 (three temporaries, any beta)              */
     WS_AUTO = 5,             /* schedule, depth and base chosen by the autotuner   */
     WS_OVR = 6,              /* Table 5: C = A*B, one temporary, destroys B        */
     WS_ACCR = 7,             /* Table 7: two temporaries, destroys B (square)      */
     WS_BLOCKED = 8,          /* Section 7.2 over Table 2: C in t x t blocks, see below */
-    WS_BLOCKED_ACC = 9       /* Section 7.2 over Table 9 (m == k == n, t | n)      */
+    WS_BLOCKED_ACC = 9,      /* Section 7.2 over Table 9 (m == k == n, t | n)      */
+    WS_OVL = 10,             /* Table 4: C = A*B, one temporary, destroys A (square) */
+    WS_ACR = 11              /* Table 8: any even shape, two temporaries, destroys B */
 } ws_schedule;
+
+/*
+ * The rectangular overwriting schedules (Section 5.3).  Table 8 takes any
+ * m, k, n divisible by 2^levels; its temporaries are max(m/2, k/2) x n/2
+ * and m/2 x k/2 per level (below 2n^2/3 when square).  Algorithm 1 (WS_OVERWRITE
+ * with beta == 0 and a non-square shape) needs n = min(m, k, n) dividing m
+ * and k, and n divisible by 2^levels; it cuts A, B, C into n x n squares and
+ * uses no workspace at all: with m > n the first square of C by Table 1 with
+ * its temporaries in the second, then the Table 4 products and Table 2
+ * accumulations with their temporaries in the freed square A_11 (A is
+ * destroyed, B kept); with m == n, Table 3 and then Table 6 calls with their
+ * temporaries in the freed A_1 (A and B destroyed).
+ */
 
 /*
  * Blocked accumulation (Section 7.2).  A, B and C are cut along every

@@ -481,6 +481,9 @@ const char *wsmul_schedule_name(int table) {
     case TAB_ACCR: return "table7-accumulate-overwrite-B";
     case TAB_ACC: return "table9-accumulate-two-temporaries";
     case TAB_IPMM: return "algorithm2-read-only-in-place";
+    case TAB_OVL: return "table4-overwrite-A";
+    case TAB_ACR: return "table8-accumulate-overwrite-B-rectangular";
+    case TAB_IP0VMM: return "algorithm1-in-place-overwrite-rectangular";
     case TAB_BLOCKED_HL: return "section7.2-blocked-accumulation-table2";
     case TAB_BLOCKED_ACC: return "section7.2-blocked-accumulation-table9";
     default: return "unknown";

@@ -435,6 +435,48 @@ class Emitter {
         add(C12, C12, A12);                   // 22 U5 = U4 + P3
     }
 
+    // ---- Table 4: C <- a*A*B, one temporary X ((n/2)^2); overwrites A
+    void ovl(View A, View B, View C, int64_t a, int lev, int d) {
+        if (lev == 0)
+            return gemm(A, B, C, a, 0);
+        depth_ = d;
+        const View A11 = quad(A, 0, 0), A12 = quad(A, 0, 1), A21 = quad(A, 1, 0), A22 = quad(A, 1, 1);
+        const View B11 = quad(B, 0, 0), B12 = quad(B, 0, 1), B21 = quad(B, 1, 0), B22 = quad(B, 1, 1);
+        const View C11 = quad(C, 0, 0), C12 = quad(C, 0, 1), C21 = quad(C, 1, 0), C22 = quad(C, 1, 1);
+        const int64_t h = C.rows / 2;
+        Frame f = frame(d, {{h, h}});
+        const View X = f.v[0];
+        sub(C22, A11, A21);                    // 1  S3
+        add(A21, A21, A22);                    // 2  S1
+        sub(C12, A21, A11);                    // 3  S2 = S1 - A11
+        sub(C21, B12, B11);                    // 4  T1
+        ovl(A11, B11, C11, a, lev - 1, d + 1); // 5  P1
+        depth_ = d;
+        sub(A11, B22, B12);                    // 6  T3
+        ip(C22, A11, X, a, lev - 1, d + 1);    // 7  P7 = S3 T3
+        depth_ = d;
+        sub(A11, B22, C21);                    // 8  T2 = B22 - T1
+        ip(A21, C21, C22, a, lev - 1, d + 1);  // 9  P5 = S1 T1
+        depth_ = d;
+        sub(C21, A12, C12);                    // 10 S4 = A12 - S2
+        ovl(C21, B22, A21, a, lev - 1, d + 1); // 11 P3 = S4 B22
+        ovl(C12, A11, C21, a, lev - 1, d + 1); // 12 P6 = S2 T2
+        depth_ = d;
+        sub(A11, A11, B21);                    // 13 T4 = T2 - B21
+        add(C21, C11, C21);                    // 14 U2 = P1 + P6
+        add(C12, C21, C22);                    // 15 U4 = U2 + P5
+        add(C21, C21, X);                      // 16 U3 = U2 + P7
+        add(C22, C21, C22);                    // 17 U7 = U3 + P5
+        add(C12, C12, A21);                    // 18 U5 = U4 + P3
+        ovl(A12, B21, X, a, lev - 1, d + 1);   // 19 P2
+        depth_ = d;
+        add(C11, C11, X);                      // 20 U1 = P1 + P2
+        ip(A22, A11, A21, a, lev - 1, d + 1);  // 21 P4 = A22 T4
+        depth_ = d;
+        sub(C21, C21, A21);                    // 22 U6 = U3 - P4
+        release(f);
+    }
+
     // ---- Table 5: C <- a*A*B, one temporary X ((n/2)^2); overwrites B
     void ovr(View A, View B, View C, int64_t a, int lev, int d) {
         if (lev == 0)
@@ -564,6 +606,50 @@ class Emitter {
         release(f);
     }
 
+    // ---- Table 8: C <- a*A*B + b*C for any even shape, temporaries
+    // X (max(m/2, k/2) x n/2: a T block, then products) and Y (m/2 x k/2: S
+    // blocks); overwrites B only.  Rows 12 and 22 are Table 1 calls.
+    void acr(View A, View B, View C, int64_t a, int64_t b, int lev, int d) {
+        if (lev == 0)
+            return gemm(A, B, C, a, b);
+        depth_ = d;
+        const View A11 = quad(A, 0, 0), A12 = quad(A, 0, 1), A21 = quad(A, 1, 0), A22 = quad(A, 1, 1);
+        const View B11 = quad(B, 0, 0), B12 = quad(B, 0, 1), B21 = quad(B, 1, 0), B22 = quad(B, 1, 1);
+        const View C11 = quad(C, 0, 0), C12 = quad(C, 0, 1), C21 = quad(C, 1, 0), C22 = quad(C, 1, 1);
+        const int64_t h = A.rows / 2, kk = A.cols / 2, w = B.cols / 2;
+        Frame f = frame(d, {{std::max(h, kk), w}, {h, kk}});
+        const View XT = block(f.v[0], 0, 0, kk, w), XP = block(f.v[0], 0, 0, h, w), Y = f.v[1];
+        sub(C22, C22, C12);                           // 1  Z1
+        sub(XT, B12, B11);                            // 2  T1
+        sub(C21, C21, C22);                           // 3  Z2 = C21 - Z1
+        sub(B12, B22, B12);                           // 4  T3
+        sub(Y, A11, A21);                             // 5  S3
+        acr(Y, B12, C22, a, b, lev - 1, d + 1);       // 6  P7 + b Z1
+        depth_ = d;
+        add(Y, A21, A22);                             // 7  S1
+        sub(B12, B22, XT);                            // 8  T2 = B22 - T1
+        acr(Y, XT, C12, a, b, lev - 1, d + 1);        // 9  P5 + b C12
+        depth_ = d;
+        sub(XT, B12, B21);                            // 10 T4 = T2 - B21
+        acr(A22, XT, C21, a, neg(b), lev - 1, d + 1); // 11 P4 - b Z2
+        t1(A11, B11, XP, a, lev - 1, d + 1);          // 12 P1
+        acr(A12, B21, C11, a, b, lev - 1, d + 1);     // 13 P2 + b C11
+        depth_ = d;
+        add(C11, XP, C11);                            // 14 U1 = P1 + P2
+        sub(Y, Y, A11);                               // 15 S2 = S1 - A11
+        acr(Y, B12, XP, a, 1, lev - 1, d + 1);        // 16 U2 = a S2 T2 + P1
+        depth_ = d;
+        add(C22, XP, C22);                            // 17 U3 = U2 + P7
+        sub(C21, C22, C21);                           // 18 U6 = U3 - P4
+        add(C22, C22, C12);                           // 19 U7 = U3 + P5
+        add(XP, XP, C12);                             // 20 U4 = U2 + P5
+        sub(Y, A12, Y);                               // 21 S4 = A12 - S2
+        t1(Y, B22, C12, a, lev - 1, d + 1);           // 22 P3 = S4 B22
+        depth_ = d;
+        add(C12, XP, C12);                            // 23 U5 = U4 + P3
+        release(f);
+    }
+
     // ---- Table 9: C <- a*A*B + b*C, two temporaries; A and B read only
     void acc(View A, View B, View C, int64_t a, int64_t b, int lev, int d) {
         if (lev == 0)
@@ -637,6 +723,40 @@ class Emitter {
         }
         regions_.pop_back();
         ipmm(A2, B2, C22, a, L, dd + 1);
+    }
+
+    // ---- Algorithm 1, with the cutting into squares of its section:
+    // C <- a*A*B with no extra memory, s = n = min(m, k, n) dividing m and k;
+    // A, B, C cut into s x s squares A_ij, B_j, C_i.  With m/s >= 2: C_1 by
+    // Table 1 with its temporaries in C_2, then A_11 is free space for the
+    // Table 4 products C_i = A_i1 B_1 (i >= 2, overwriting A_i1) and the
+    // Table 2 accumulations C_i += A_ij B_j (j >= 2).  With m = s: C by
+    // Table 3 from A_1 and B_1, then C += A_j B_j by Table 6 with temporaries
+    // in the freed A_1.  Temporaries in a free square are placed as in
+    // Algorithm 2 (quadrants, callees in the bottom-right one).
+    void ip0vmm(View A, View B, View C, int64_t a, int L) {
+        const int64_t s = B.cols, m0 = A.rows / s, k0 = A.cols / s;
+        auto Ab = [&](int64_t i, int64_t j) { return block(A, i * s, j * s, s, s); };
+        auto Bb = [&](int64_t j) { return block(B, j * s, 0, s, s); };
+        auto Cb = [&](int64_t i) { return block(C, i * s, 0, s, s); };
+        if (m0 == 1) {
+            ip(Ab(0, 0), Bb(0), Cb(0), a, L, 0);
+            regions_.push_back(Ab(0, 0));
+            for (int64_t j = 1; j < k0; ++j)
+                aclr(Ab(0, j), Bb(j), Cb(0), a, 1, L, 0);
+            regions_.pop_back();
+            return;
+        }
+        regions_.push_back(Cb(1));
+        t1(Ab(0, 0), Bb(0), Cb(0), a, L, 0);
+        regions_.pop_back();
+        regions_.push_back(Ab(0, 0));
+        for (int64_t i = 1; i < m0; ++i)
+            ovl(Ab(i, 0), Bb(0), Cb(i), a, L, 0);
+        for (int64_t j = 1; j < k0; ++j)
+            for (int64_t i = 0; i < m0; ++i)
+                hl(Ab(i, j), Bb(j), Cb(i), a, 1, L, 0);
+        regions_.pop_back();
     }
 
     // ---- Section 7.2: C <- a*A*B + b*C as a t x t grid of blocks.  Block
@@ -733,6 +853,15 @@ void run(Emitter &e, const PlanKey &key) {
     case TAB_ACCR:
         e.accr(A, B, C, a, b, L, 0);
         break;
+    case TAB_OVL:
+        e.ovl(A, B, C, a, L, 0);
+        break;
+    case TAB_ACR:
+        e.acr(A, B, C, a, b, L, 0);
+        break;
+    case TAB_IP0VMM:
+        e.ip0vmm(A, B, C, a, L);
+        break;
     case TAB_IPMM:
         e.ipmm(A, B, C, a, L, 0);
         break;
@@ -762,6 +891,11 @@ std::vector<int64_t> block_parts(int64_t d, int t, int L) {
     return out;
 }
 
+bool ip0vmm_supported(int64_t m, int64_t k, int64_t n, int levels) {
+    return n > 0 && levels >= 0 && levels < 62 && n <= m && n <= k && m % n == 0 && k % n == 0 &&
+           n % (int64_t(1) << levels) == 0;
+}
+
 bool ipmm_supported(int64_t m, int64_t k, int64_t n, int levels) {
     if (m != n || levels < 0)
         return false;
@@ -788,6 +922,8 @@ Resolved resolve_schedule(int schedule, int64_t m, int64_t k, int64_t n, bool be
     }
     const bool square = m == k && k == n;
     const bool divisible = levels < 62 && m % (int64_t(1) << levels) == 0;
+    const bool all_divisible = divisible && k % (int64_t(1) << levels) == 0 &&
+                               n % (int64_t(1) << levels) == 0;
     auto shape_error = [&](const char *what) {
         r.status = WS_ESHAPE;
         r.error = what;
@@ -807,9 +943,33 @@ Resolved resolve_schedule(int schedule, int64_t m, int64_t k, int64_t n, bool be
         }
         break;
     case WS_OVERWRITE:
-        r.table = beta_nonzero ? TAB_ACLR : TAB_IP;
-        if (!square || !divisible)
-            shape_error("the overwriting schedules (Tables 3 and 6) need m == k == n divisible by 2^levels");
+        if (square) {
+            r.table = beta_nonzero ? TAB_ACLR : TAB_IP;
+            if (!divisible)
+                shape_error("the square overwriting schedules (Tables 3 and 6) need n divisible by 2^levels");
+        } else if (!beta_nonzero) {
+            r.table = TAB_IP0VMM;
+            if (!ip0vmm_supported(m, k, n, levels))
+                shape_error("Algorithm 1 needs n = min(m, k, n) dividing m and k, and n divisible by 2^levels");
+        } else {
+            r.table = TAB_ACR;
+            if (!all_divisible)
+                shape_error("Table 8 needs m, k and n divisible by 2^levels");
+        }
+        break;
+    case WS_OVL:
+        r.table = TAB_OVL;
+        if (beta_nonzero) {
+            r.status = WS_ESCHEDULE;
+            r.error = "Table 4 computes C = alpha*A*B only (beta must be 0 mod p)";
+        } else if (!square || !divisible) {
+            shape_error("Table 4 needs m == k == n divisible by 2^levels");
+        }
+        break;
+    case WS_ACR:
+        r.table = TAB_ACR;
+        if (!all_divisible)
+            shape_error("Table 8 needs m, k and n divisible by 2^levels");
         break;
     case WS_READONLY_INPLACE:
         r.table = TAB_IPMM;
@@ -889,7 +1049,7 @@ int64_t workspace_elems(int table, int64_t m, int64_t k, int64_t n, int levels, 
     key.ldc = n;
     key.alpha = 1;
     key.beta = (table == TAB_HL || table == TAB_ACC || table == TAB_ACLR || table == TAB_ACCR ||
-                table == TAB_BLOCKED_HL || table == TAB_BLOCKED_ACC)
+                table == TAB_ACR || table == TAB_BLOCKED_HL || table == TAB_BLOCKED_ACC)
                    ? 1
                    : 0;
     key.table = table;

@@ -26,10 +26,13 @@ enum Table : int {
     TAB_T1 = 1,     // Table 1
     TAB_HL = 2,     // Table 2
     TAB_IP = 3,     // Table 3
+    TAB_OVL = 4,    // Table 4
     TAB_OVR = 5,    // Table 5
     TAB_ACLR = 6,   // Table 6
     TAB_ACCR = 7,   // Table 7
+    TAB_ACR = 8,    // Table 8
     TAB_ACC = 9,    // Table 9
+    TAB_IP0VMM = 11,  // Algorithm 1
     TAB_IPMM = 12,  // Algorithm 2
     TAB_BLOCKED_HL = 13,   // Section 7.2, t x t blocks over Table 2
     TAB_BLOCKED_ACC = 14,  // Section 7.2, t x t blocks over Table 9
@@ -76,5 +79,6 @@ int64_t workspace_elems(int table, int64_t m, int64_t k, int64_t n, int levels, 
 std::vector<int64_t> block_parts(int64_t d, int t, int L);
 
 bool ipmm_supported(int64_t m, int64_t k, int64_t n, int levels);
+bool ip0vmm_supported(int64_t m, int64_t k, int64_t n, int levels);
 
 }  // namespace wsmul

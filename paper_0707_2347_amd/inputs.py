@@ -25,6 +25,10 @@ WORKLOADS = {
                                          levels=1),
     "t1_16384_p1048573": dict(seed=4, m=16384, k=16384, n=16384, p=1048573, alpha=1,
                               beta=0, dtype="f64", schedules=("two_temp",), levels=None),
+    # the largest shape of the paper's rectangular timings (m = n < k)
+    "overwrite_8192x16384x8192_p8388593": dict(seed=6, m=8192, k=16384, n=8192, p=8388593,
+                                               alpha=1, beta=0, dtype="f64",
+                                               schedules=("overwrite",), levels=1),
 }
 
 

@@ -238,6 +238,54 @@ def test_acc_4096_blocked(schedule, levels, t, want):
     assert np.array_equal(A2, A) and np.array_equal(B2, B)
 
 
+FAMILY = [
+    # selector, shape, levels, beta, oracle schedule
+    (capi.WS_OVL, (128, 128, 128), 1, 0, "ovl"), (capi.WS_OVL, (256, 256, 256), 3, 0, "ovl"),
+    (capi.WS_ACR, (256, 128, 512), 2, 11, "acr"), (capi.WS_ACR, (512, 256, 128), 3, 11, "acr"),
+    (capi.WS_ACR, (192, 64, 320), 1, 0, "acr"), (capi.WS_ACR, (256, 256, 256), 2, 11, "acr"),
+    (capi.WS_OVERWRITE, (256, 512, 128), 2, 0, "ip0vmm"),
+    (capi.WS_OVERWRITE, (384, 256, 128), 1, 0, "ip0vmm"),
+    (capi.WS_OVERWRITE, (128, 384, 128), 3, 0, "ip0vmm"),
+    (capi.WS_OVERWRITE, (256, 128, 128), 2, 0, "ip0vmm"),
+    (capi.WS_OVERWRITE, (512, 512, 256), 2, 0, "ip0vmm"),
+    (capi.WS_OVERWRITE, (256, 128, 512), 2, 11, "acr"),
+]
+
+
+@pytest.mark.parametrize("dtype", [capi.WS_F64, capi.WS_I64])
+@pytest.mark.parametrize("schedule,shape,levels,beta,name", FAMILY)
+def test_overwrite_family(schedule, shape, levels, beta, name, dtype):
+    """Tables 4 and 8 and Algorithm 1: the product, and the final state of the
+    inputs they overwrite, against the oracle's replay."""
+    m, k, n = shape
+    print("family", schedule, shape, levels, beta, dtype, flush=True)
+    p = 8388593 if levels % 2 else 65521
+    A, B, C = inputs.uniform(m * 3 + k * 5 + n * 11 + levels, m, k, n, p, with_c=True)
+    st, C2, A2, B2 = call(schedule, A, B, C, 9, beta, p, levels, dtype=dtype)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, 9, beta, p))
+    r = replay(name, A, B, C, 9, beta, p, levels)
+    assert np.array_equal(C2, r.C)
+    assert np.array_equal(A2, r.A) and np.array_equal(B2, r.B)
+    assert capi.wsmul_get_stats().workspace_bytes == 8 * int(r.peak)
+
+
+@pytest.mark.parametrize("shape,levels", [((4096, 8192, 4096), 2), ((8192, 8192, 4096), 2)])
+def test_algorithm1_full_size(shape, levels):
+    """Algorithm 1 on a shape the paper times (m = n < k: Table 3, then
+    Table 6 in the freed block) and on its own case n < min(m, k)."""
+    m, k, n = shape
+    p = 8388593
+    A, B, _ = inputs.uniform(41, m, k, n, p)
+    st, C2, _, B2 = call(capi.WS_OVERWRITE, A, B, None, 1, 0, p, levels)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    _sampled(A, B, None, 1, 0, p, C2)
+    s = capi.wsmul_get_stats()
+    assert s.workspace_bytes == 0 and s.internal_alloc_bytes == 0
+    if m > n:
+        assert np.array_equal(B2, B)
+
+
 def test_attached_workspace_exact_size_and_no_hidden_allocation():
     t = __import__("torch")
     p = 65521

@@ -123,6 +123,60 @@ def test_blocked_plan_reproduces_oracle(schedule, shape, levels, t, beta, fuse):
     assert capi.wsmul_schedule_name(info.schedule).startswith("section7.2-blocked")
 
 
+FAMILY = [
+    # selector, shape, levels, beta, oracle schedule
+    (capi.WS_OVL, (32, 32, 32), 1, 0, "ovl"), (capi.WS_OVL, (64, 64, 64), 3, 0, "ovl"),
+    (capi.WS_ACR, (32, 32, 32), 2, 7, "acr"), (capi.WS_ACR, (64, 32, 128), 2, 7, "acr"),
+    (capi.WS_ACR, (128, 64, 32), 3, 0, "acr"), (capi.WS_ACR, (48, 16, 80), 1, 7, "acr"),
+    (capi.WS_OVERWRITE, (64, 32, 128), 2, 7, "acr"),
+    (capi.WS_OVERWRITE, (64, 128, 32), 2, 0, "ip0vmm"),
+    (capi.WS_OVERWRITE, (96, 64, 32), 1, 0, "ip0vmm"),
+    (capi.WS_OVERWRITE, (32, 96, 32), 3, 0, "ip0vmm"),
+    (capi.WS_OVERWRITE, (64, 32, 32), 2, 0, "ip0vmm"),
+    (capi.WS_OVERWRITE, (128, 128, 64), 2, 0, "ip0vmm"),
+]
+
+
+@pytest.mark.parametrize("fuse", [True, False])
+@pytest.mark.parametrize("schedule,shape,levels,beta,name", FAMILY)
+def test_overwrite_family_plan_reproduces_oracle(schedule, shape, levels, beta, name, fuse):
+    """Tables 4 and 8 and Algorithm 1: the plan's product, the final state of
+    the inputs it overwrites, its temporaries and its additions equal the
+    oracle's replay."""
+    m, k, n = shape
+    p = 8388593 if levels % 2 else 65521
+    alpha = 3
+    (A, B, C), (A2, B2, C2), info = _interp(schedule, m, k, n, p, alpha, beta, levels,
+                                             seed=m + k * 3 + n * 7 + levels, fuse=fuse)
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, alpha, beta, p))
+    r = replay(name, A, B, C, alpha, beta, p, levels)
+    assert np.array_equal(A2, r.A) and np.array_equal(B2, r.B)
+    rs = replay_shape(name, m, k, n, p, levels, beta_nonzero=bool(beta))
+    assert info.workspace_bytes == 8 * rs.peak
+    assert info.element_additions == rs.adds
+    assert capi.wsmul_schedule_name(info.schedule).startswith(
+        {"ovl": "table4", "acr": "table8", "ip0vmm": "algorithm1"}[name])
+
+
+def test_overwrite_family_argument_errors():
+    import ctypes
+    s = capi.ws_stats()
+
+    def status(m, k, n, schedule, levels, beta):
+        a = capi.make_args(m, k, n, 65521, A=16, B=16, C=16, beta=beta, schedule=schedule,
+                           levels=levels)
+        return capi.lib().wsmul_plan_info(ctypes.byref(a), ctypes.byref(s))
+
+    assert status(32, 32, 32, capi.WS_OVL, 1, 3) == capi.WS_ESCHEDULE      # Table 4: no beta
+    assert status(32, 64, 32, capi.WS_OVL, 1, 0) == capi.WS_ESHAPE         # Table 4: square
+    assert status(48, 32, 40, capi.WS_ACR, 4, 1) == capi.WS_ESHAPE         # 48 % 16 != 0
+    assert status(48, 64, 32, capi.WS_OVERWRITE, 1, 0) == capi.WS_ESHAPE   # 32 does not divide 48
+    assert status(32, 64, 64, capi.WS_OVERWRITE, 1, 0) == capi.WS_ESHAPE   # n is not the smallest
+    assert status(64, 128, 32, capi.WS_OVERWRITE, 6, 0) == capi.WS_ESHAPE  # 32 % 64 != 0
+    assert status(64, 128, 32, capi.WS_OVERWRITE, 5, 0) == capi.WS_OK
+    assert status(64, 128, 32, capi.WS_OVERWRITE, 2, 1) == capi.WS_OK      # Table 8
+
+
 def test_blocked_workload_bytes():
     """The accumulating 4096^3 product with three levels: t = 2 needs a
     quarter (Table 2) or a sixth (Table 9) of n^2 entries at most."""
