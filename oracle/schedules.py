@@ -65,6 +65,11 @@ Readings of the paper taken here (where it is silent or garbled):
   by Table 6 with temporaries in the freed A_1.  Temporaries in a free
   square are laid out as in Algorithm 2 (quadrants, recursion in the
   bottom-right one).
+* Algorithm 2 with Table 9 for the accumulating chunks (the remark closing
+  Section 7.1, square case): every chunk after the first runs Table 9 instead
+  of Table 2, which needs square chunk products (k >= n/2, so K = s/2 at every
+  depth); Table 9's two temporaries take the top-left and bottom-left
+  quadrants of the lent region.
 * Algorithm 2 with the depth parameter L: at depth d < L the three quadrant
   products are Winograd calls of depth L - d, with inner dimension cut in
   chunks of K = min(s/2, k); at depth L the remaining corner is a classical
@@ -78,7 +83,7 @@ from contextlib import contextmanager
 import numpy as np
 
 SCHEDULES = ("classical", "t1", "hl", "ip", "ovr", "aclr", "accr", "acc", "ipmm",
-             "blocked", "blocked_acc", "ovl", "acr", "ip0vmm")
+             "blocked", "blocked_acc", "ovl", "acr", "ip0vmm", "ipmm_acc")
 OVERWRITES = {"ip": "AB", "ovr": "B", "aclr": "AB", "accr": "B", "ovl": "A", "acr": "B",
               "ip0vmm": "AB"}
 
@@ -548,11 +553,12 @@ class Winograd:
             self.accr(A22, Y, C21, -a, 1, lev - 1)   # 24 U6 = U3 - a A22 T4
 
     # ------------------------------------------------------ Algorithm 2 (IPMM)
-    def ipmm(self, A, B, C, a, L, d=0):
+    def ipmm(self, A, B, C, a, L, d=0, acc_base=False):
         """Algorithm 2: C <- a*A*B with no extra memory and A, B read only.
         The three quadrant products run as Table 1 (first inner chunk) and
-        Table 2 (remaining chunks) calls whose temporaries live in C22; C22
-        itself is then computed by the same algorithm."""
+        Table 2 (remaining chunks; Table 9 with ``acc_base``) calls whose
+        temporaries live in C22; C22 itself is then computed by the same
+        algorithm."""
         self.calls["ipmm"] += 1
         s = C.shape[0]
         k = A.shape[1]
@@ -560,6 +566,7 @@ class Winograd:
             return self.leaf(A, B, C, a, 0, False)
         h = s // 2
         K = min(h, k)
+        accumulate = self.acc if acc_base else self.hl
         if k % K:
             raise AssertionError("inner dimension is not a multiple of the chunk")
         C11, C12, C21, C22 = quads(C)
@@ -578,12 +585,12 @@ class Winograd:
                     self.t1(a1, b2, C12, a, lev)
                     self.t1(a2, b1, C21, a, lev)
                 else:
-                    self.hl(a1, b1, C11, a, 1, lev)
-                    self.hl(a1, b2, C12, a, 1, lev)
-                    self.hl(a2, b1, C21, a, 1, lev)
+                    accumulate(a1, b1, C11, a, 1, lev)
+                    accumulate(a1, b2, C12, a, 1, lev)
+                    accumulate(a2, b1, C21, a, 1, lev)
         finally:
             self._regions.pop()
-        self.ipmm(A2, B2, C22, a, L, d + 1)
+        self.ipmm(A2, B2, C22, a, L, d + 1, acc_base)
 
     # ------------------------------------------------------ Algorithm 1 (IP0vMM)
     def ip0vmm(self, A, B, C, a, lev):
@@ -739,9 +746,11 @@ def _check(schedule, m, k, n, p, beta, L, t=2):
                              % schedule)
     if schedule == "acc" and not (m == k == n):
         raise ValueError("schedule acc needs a square shape")
-    if schedule == "ipmm" and not ipmm_shape_ok(m, k, n, L):
+    if schedule in ("ipmm", "ipmm_acc") and not ipmm_shape_ok(m, k, n, L):
         raise ValueError("shape not supported by ipmm at this depth")
-    if beta % p and schedule in ("ovl", "ip0vmm"):
+    if schedule == "ipmm_acc" and 2 * k < n:
+        raise ValueError("Table 9 inside Algorithm 2 needs square chunks (k >= n/2)")
+    if beta % p and schedule in ("ovl", "ip0vmm", "ipmm_acc"):
         raise ValueError("schedule %s computes C = A*B only (beta must be 0)" % schedule)
     if schedule == "ovl" and (not (m == k == n) or m % (2 ** L)):
         raise ValueError("schedule ovl needs a square shape divisible by 2**levels")
@@ -780,6 +789,8 @@ def _run(w, schedule, A, B, C, a, b, L, t=2):
         w.acr(A, B, C, a, b, L)
     elif schedule == "ip0vmm":
         w.ip0vmm(A, B, C, a, L)
+    elif schedule == "ipmm_acc":
+        w.ipmm(A, B, C, a, L, acc_base=True)
     elif schedule == "blocked":
         w.blocked(w.hl, A, B, C, a, b, t, L)
     elif schedule == "blocked_acc":

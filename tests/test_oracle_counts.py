@@ -454,3 +454,25 @@ def test_ip0vmm_arithmetic_and_no_memory(shape, l):
         assert r.ops == m0 * W1(n, l) + m0 * (k0 - 1) * W2(n, l)
     if l == n.bit_length() - 1 and m0 > 1:                      # full recursion
         assert r.ops == m0 * (6 * 7**l - 5 * 4**l) + m0 * (k0 - 1) * (6 * 7**l - 4 * 4**l)
+
+
+def G9(s, k, L, d=0):
+    """Theorem 1's recurrence with Table 9 for the accumulating chunks."""
+    if d == L:
+        return s * s * (2 * k - 1)
+    h = s // 2
+    K = min(h, k)
+    lev = L - d
+    return 3 * W1r(h, K, h, lev) + 3 * (k // K - 1) * W9(h, lev) + G9(h, k, L, d + 1)
+
+
+@pytest.mark.parametrize("shape,L", [((64, 64, 64), 1), ((64, 64, 64), 3), ((64, 32, 64), 2),
+                                     ((128, 256, 128), 2), ((32, 128, 32), 3)])
+def test_ipmm_acc_recurrence(shape, L):
+    """Algorithm 2 with Table 9 accumulations: Theorem 1's recurrence with
+    W9 in place of W2, no extra memory; never cheaper than with Table 2."""
+    m, k, n = shape
+    r = replay_shape("ipmm_acc", m, k, n, levels=L)
+    assert r.ops == G9(n, k, L)
+    assert r.peak == 0
+    assert r.ops >= replay_shape("ipmm", m, k, n, levels=L).ops

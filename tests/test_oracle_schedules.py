@@ -421,3 +421,23 @@ def test_overwrite_family_rejects_unsupported_shapes():
     A3, B3, _ = inputs.uniform(31, 32, 64, 64, P)
     with pytest.raises(ValueError):
         replay("ip0vmm", A3, B3, None, 1, 0, P, 1)    # n is not the smallest dimension
+
+
+# ------------------- Algorithm 2 with Table 9 accumulations (end of Section 7.1)
+@pytest.mark.parametrize("p", [P, 8388593])
+@pytest.mark.parametrize("shape,levels", [((64, 64, 64), 1), ((64, 64, 64), 3), ((64, 128, 64), 2),
+                                          ((32, 64, 32), 2), ((64, 32, 64), 2)])
+def test_ipmm_acc_value_with_garbage(shape, levels, p):
+    m, k, n = shape
+    A, B, _ = inputs.uniform(zlib.crc32(repr(("ipmm_acc", shape, levels)).encode()), m, k, n, p)
+    for seed, alpha in enumerate([1, 3, p - 1]):
+        r = replay("ipmm_acc", A, B, None, alpha, 0, p, levels, garbage_seed=seed)
+        assert np.array_equal(r.C, o1(A, B, None, alpha, 0, p))
+        assert np.array_equal(r.A, A) and np.array_equal(r.B, B)
+        assert r.peak == 0 and r.allocated == 0
+
+
+def test_ipmm_acc_needs_square_chunks():
+    A, B, _ = inputs.uniform(32, 64, 16, 64, P)
+    with pytest.raises(ValueError):
+        replay("ipmm_acc", A, B, None, 1, 0, P, 2)        # k < n/2: chunks are not square
