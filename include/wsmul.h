@@ -74,7 +74,9 @@ typedef enum {
     WS_BLOCKED = 8,          /* Section 7.2 over Table 2: C in t x t blocks, see below */
     WS_BLOCKED_ACC = 9,      /* Section 7.2 over Table 9 (m == k == n, t | n)      */
     WS_OVL = 10,             /* Table 4: C = A*B, one temporary, destroys A (square) */
-    WS_ACR = 11              /* Table 8: any even shape, two temporaries, destroys B */
+    WS_ACR = 11,             /* Table 8: any even shape, two temporaries, destroys B */
+    WS_IPMM_ACC = 12         /* Algorithm 2 with Table 9 for the accumulating chunks
+                                (end of Section 7.1; beta == 0, k >= n/2)          */
 } ws_schedule;
 
 /*

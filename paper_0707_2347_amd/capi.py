@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libwsmul.so")
 WS_OK, WS_EINVAL, WS_ESHAPE, WS_EMODULUS, WS_ERANGE, WS_ESCHEDULE, WS_ENOMEM, WS_EHIP = range(8)
 # ws_schedule
 (WS_CLASSICAL, WS_TWO_TEMP, WS_OVERWRITE, WS_READONLY_INPLACE, WS_HL_THREE_TEMP, WS_AUTO,
- WS_OVR, WS_ACCR, WS_BLOCKED, WS_BLOCKED_ACC, WS_OVL, WS_ACR) = range(12)
+ WS_OVR, WS_ACCR, WS_BLOCKED, WS_BLOCKED_ACC, WS_OVL, WS_ACR, WS_IPMM_ACC) = range(13)
 WS_F64, WS_I64 = 0, 1
 WS_BASE_AUTO, WS_BASE_F64_MFMA, WS_BASE_I8_LIMBS = 0, 1, 2
 WS_FLAG_CHECK, WS_FLAG_NOFUSE, WS_FLAG_TRACE, WS_FLAG_SYNC = 1, 2, 4, 8
@@ -27,7 +27,8 @@ WS_OP_ADD, WS_OP_GEMM = 0, 1
 SCHEDULES = {"classical": WS_CLASSICAL, "two_temp": WS_TWO_TEMP, "overwrite": WS_OVERWRITE,
              "readonly_inplace": WS_READONLY_INPLACE, "hl_three_temp": WS_HL_THREE_TEMP,
              "auto": WS_AUTO, "ovr": WS_OVR, "accr": WS_ACCR, "blocked": WS_BLOCKED,
-             "blocked_acc": WS_BLOCKED_ACC, "ovl": WS_OVL, "acr": WS_ACR}
+             "blocked_acc": WS_BLOCKED_ACC, "ovl": WS_OVL, "acr": WS_ACR,
+             "ipmm_acc": WS_IPMM_ACC}
 
 _i64, _i32, _u32, _u64, _vp, _dbl = (ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
                                      ctypes.c_uint64, ctypes.c_void_p, ctypes.c_double)

@@ -271,7 +271,7 @@ extern "C" int wsmul_autotune(int64_t m, int64_t k, int64_t n, int64_t p, int dt
         key.schedule != WS_OVERWRITE && key.schedule != WS_READONLY_INPLACE &&
         key.schedule != WS_HL_THREE_TEMP && key.schedule != WS_OVR && key.schedule != WS_ACCR &&
         key.schedule != WS_BLOCKED && key.schedule != WS_BLOCKED_ACC && key.schedule != WS_OVL &&
-        key.schedule != WS_ACR) {
+        key.schedule != WS_ACR && key.schedule != WS_IPMM_ACC) {
         set_error("wsmul_autotune: unknown schedule");
         return WS_ESCHEDULE;
     }

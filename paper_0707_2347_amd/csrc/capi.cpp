@@ -481,6 +481,7 @@ const char *wsmul_schedule_name(int table) {
     case TAB_ACCR: return "table7-accumulate-overwrite-B";
     case TAB_ACC: return "table9-accumulate-two-temporaries";
     case TAB_IPMM: return "algorithm2-read-only-in-place";
+    case TAB_IPMM_ACC: return "algorithm2-read-only-in-place-table9";
     case TAB_OVL: return "table4-overwrite-A";
     case TAB_ACR: return "table8-accumulate-overwrite-B-rectangular";
     case TAB_IP0VMM: return "algorithm1-in-place-overwrite-rectangular";

@@ -695,10 +695,11 @@ class Emitter {
 
     // ---- Algorithm 2: C <- a*A*B with no extra memory, A and B read only.
     // At depth dd < L the three quadrant products run as Table 1 (first
-    // inner chunk) and Table 2 (the other chunks) of depth L - dd, with their
-    // temporaries in C22; C22 is then computed the same way.  At depth L the
+    // inner chunk) and Table 2 (the other chunks; Table 9 with acc_base, for
+    // square chunks) of depth L - dd, with their temporaries in C22; C22 is
+    // then computed the same way.  At depth L the
     // remaining corner is one classical product over the whole inner dimension.
-    void ipmm(View A, View B, View C, int64_t a, int L, int dd) {
+    void ipmm(View A, View B, View C, int64_t a, int L, int dd, bool acc_base = false) {
         const int64_t s = C.rows, k = A.cols;
         if (dd == L || s < 2 || k == 0)
             return gemm(A, B, C, a, 0);
@@ -715,6 +716,10 @@ class Emitter {
                 t1(a1, b1, C11, a, lev, 0);
                 t1(a1, b2, C12, a, lev, 0);
                 t1(a2, b1, C21, a, lev, 0);
+            } else if (acc_base) {
+                acc(a1, b1, C11, a, 1, lev, 0);
+                acc(a1, b2, C12, a, 1, lev, 0);
+                acc(a2, b1, C21, a, 1, lev, 0);
             } else {
                 hl(a1, b1, C11, a, 1, lev, 0);
                 hl(a1, b2, C12, a, 1, lev, 0);
@@ -722,7 +727,7 @@ class Emitter {
             }
         }
         regions_.pop_back();
-        ipmm(A2, B2, C22, a, L, dd + 1);
+        ipmm(A2, B2, C22, a, L, dd + 1, acc_base);
     }
 
     // ---- Algorithm 1, with the cutting into squares of its section:
@@ -865,6 +870,9 @@ void run(Emitter &e, const PlanKey &key) {
     case TAB_IPMM:
         e.ipmm(A, B, C, a, L, 0);
         break;
+    case TAB_IPMM_ACC:
+        e.ipmm(A, B, C, a, L, 0, true);
+        break;
     case TAB_BLOCKED_HL:
     case TAB_BLOCKED_ACC:
         e.blocked(key.table == TAB_BLOCKED_ACC, A, B, C, a, b, key.blocks, L);
@@ -955,6 +963,16 @@ Resolved resolve_schedule(int schedule, int64_t m, int64_t k, int64_t n, bool be
             r.table = TAB_ACR;
             if (!all_divisible)
                 shape_error("Table 8 needs m, k and n divisible by 2^levels");
+        }
+        break;
+    case WS_IPMM_ACC:
+        r.table = TAB_IPMM_ACC;
+        if (beta_nonzero) {
+            r.status = WS_ESCHEDULE;
+            r.error = "Algorithm 2 computes C = alpha*A*B only (beta must be 0 mod p)";
+        } else if (!ipmm_supported(m, k, n, levels) || 2 * k < n) {
+            shape_error("Algorithm 2 with Table 9 needs the shapes of Algorithm 2 and k >= n/2 "
+                        "(square chunks)");
         }
         break;
     case WS_OVL:

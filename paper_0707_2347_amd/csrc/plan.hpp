@@ -34,6 +34,7 @@ enum Table : int {
     TAB_ACC = 9,    // Table 9
     TAB_IP0VMM = 11,  // Algorithm 1
     TAB_IPMM = 12,  // Algorithm 2
+    TAB_IPMM_ACC = 15,  // Algorithm 2 with Table 9 accumulations
     TAB_BLOCKED_HL = 13,   // Section 7.2, t x t blocks over Table 2
     TAB_BLOCKED_ACC = 14,  // Section 7.2, t x t blocks over Table 9
 };

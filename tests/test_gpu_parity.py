@@ -249,13 +249,16 @@ FAMILY = [
     (capi.WS_OVERWRITE, (256, 128, 128), 2, 0, "ip0vmm"),
     (capi.WS_OVERWRITE, (512, 512, 256), 2, 0, "ip0vmm"),
     (capi.WS_OVERWRITE, (256, 128, 512), 2, 11, "acr"),
+    (capi.WS_IPMM_ACC, (256, 256, 256), 3, 0, "ipmm_acc"),
+    (capi.WS_IPMM_ACC, (256, 512, 256), 2, 0, "ipmm_acc"),
+    (capi.WS_IPMM_ACC, (256, 128, 256), 1, 0, "ipmm_acc"),
 ]
 
 
 @pytest.mark.parametrize("dtype", [capi.WS_F64, capi.WS_I64])
 @pytest.mark.parametrize("schedule,shape,levels,beta,name", FAMILY)
 def test_overwrite_family(schedule, shape, levels, beta, name, dtype):
-    """Tables 4 and 8 and Algorithm 1: the product, and the final state of the
+    """Tables 4 and 8, Algorithm 1 and Algorithm 2 with Table 9: the product, and the final state of the
     inputs they overwrite, against the oracle's replay."""
     m, k, n = shape
     print("family", schedule, shape, levels, beta, dtype, flush=True)

@@ -134,6 +134,9 @@ FAMILY = [
     (capi.WS_OVERWRITE, (32, 96, 32), 3, 0, "ip0vmm"),
     (capi.WS_OVERWRITE, (64, 32, 32), 2, 0, "ip0vmm"),
     (capi.WS_OVERWRITE, (128, 128, 64), 2, 0, "ip0vmm"),
+    (capi.WS_IPMM_ACC, (64, 64, 64), 3, 0, "ipmm_acc"),
+    (capi.WS_IPMM_ACC, (64, 128, 64), 2, 0, "ipmm_acc"),
+    (capi.WS_IPMM_ACC, (64, 32, 64), 2, 0, "ipmm_acc"),
 ]
 
 
@@ -155,7 +158,8 @@ def test_overwrite_family_plan_reproduces_oracle(schedule, shape, levels, beta, 
     assert info.workspace_bytes == 8 * rs.peak
     assert info.element_additions == rs.adds
     assert capi.wsmul_schedule_name(info.schedule).startswith(
-        {"ovl": "table4", "acr": "table8", "ip0vmm": "algorithm1"}[name])
+        {"ovl": "table4", "acr": "table8", "ip0vmm": "algorithm1",
+         "ipmm_acc": "algorithm2-read-only-in-place-table9"}[name])
 
 
 def test_overwrite_family_argument_errors():
@@ -175,6 +179,8 @@ def test_overwrite_family_argument_errors():
     assert status(64, 128, 32, capi.WS_OVERWRITE, 6, 0) == capi.WS_ESHAPE  # 32 % 64 != 0
     assert status(64, 128, 32, capi.WS_OVERWRITE, 5, 0) == capi.WS_OK
     assert status(64, 128, 32, capi.WS_OVERWRITE, 2, 1) == capi.WS_OK      # Table 8
+    assert status(64, 16, 64, capi.WS_IPMM_ACC, 2, 0) == capi.WS_ESHAPE    # k < n/2
+    assert status(64, 64, 64, capi.WS_IPMM_ACC, 2, 3) == capi.WS_ESCHEDULE
 
 
 def test_blocked_workload_bytes():
