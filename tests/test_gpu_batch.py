@@ -23,7 +23,8 @@ def _mk_batch(specs, seed):
     t = _torch()
     host, dev, args = [], [], []
     rng = np.random.default_rng(seed)
-    for i, (m, k, n, p, sched, lev, beta) in enumerate(specs):
+    for i, spec in enumerate(specs):
+        m, k, n, p, sched, lev, beta = spec[:7]
         A, B, C = inputs.uniform(seed * 1000 + i, m, k, n, p, with_c=True)
         dA = t.from_numpy(A.astype(np.float64)).cuda()
         dB = t.from_numpy(B.astype(np.float64)).cuda()
@@ -33,7 +34,8 @@ def _mk_batch(specs, seed):
         dev.append((dA, dB, dC))
         args.append(capi.make_args(m, k, n, p, dA, dB, dC, alpha, beta, sched, lev,
                                    base=capi.WS_BASE_F64_MFMA,
-                                   stream=t.cuda.current_stream()))
+                                   stream=t.cuda.current_stream(),
+                                   blocks=spec[7] if len(spec) > 7 else 0))
     return host, dev, args
 
 
@@ -50,6 +52,27 @@ SPECS = [
 def test_batched_mixed():
     t = _torch()
     host, dev, args = _mk_batch(SPECS, 3)
+    st = capi.wsmul_batched(args, capi.WS_FLAG_SYNC)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    t.cuda.synchronize()
+    for (A, B, C, alpha, beta, p), (dA, dB, dC) in zip(host, dev):
+        got = dC.cpu().numpy().astype(np.int64)
+        assert np.array_equal(got, ref.matmul_mod_p(A, B, C, alpha, beta, p))
+
+
+SPECS_MORE = [
+    # the blocked accumulation of Section 7.2 (last field: t), Tables 4 and 8,
+    # Algorithm 1 and Algorithm 2 with Table 9, side by side in one batch
+    (256, 256, 256, 65521, capi.WS_BLOCKED, 2, 3, 2), (384, 384, 384, 8388593, capi.WS_BLOCKED, 1, 5, 3),
+    (256, 256, 256, 65521, capi.WS_BLOCKED_ACC, 2, 3, 2), (256, 128, 512, 65521, capi.WS_ACR, 2, 11),
+    (256, 512, 128, 8388593, capi.WS_OVERWRITE, 2, 0), (128, 384, 128, 65521, capi.WS_OVERWRITE, 2, 0),
+    (256, 256, 256, 65521, capi.WS_OVL, 2, 0), (256, 512, 256, 8388593, capi.WS_IPMM_ACC, 2, 0),
+]
+
+
+def test_batched_more_schedules():
+    t = _torch()
+    host, dev, args = _mk_batch(SPECS_MORE, 4)
     st = capi.wsmul_batched(args, capi.WS_FLAG_SYNC)
     assert st == capi.WS_OK, capi.wsmul_last_error()
     t.cuda.synchronize()
