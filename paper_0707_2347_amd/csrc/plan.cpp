@@ -1029,6 +1029,15 @@ Resolved resolve_schedule(int schedule, int64_t m, int64_t k, int64_t n, bool be
         r.status = WS_ESCHEDULE;
         r.error = "unknown schedule";
     }
+    // An empty product has nothing to schedule: m == 0 or n == 0 leaves C
+    // alone and k == 0 gives C <- beta*C, which one classical base product
+    // does for every schedule.
+    if (r.status == WS_ESHAPE && (m == 0 || k == 0 || n == 0)) {
+        r.status = WS_OK;
+        r.error.clear();
+        r.table = TAB_CLASSICAL;
+        r.levels = 0;
+    }
     return r;
 }
 

@@ -289,6 +289,21 @@ def test_algorithm1_full_size(shape, levels):
         assert np.array_equal(B2, B)
 
 
+@pytest.mark.parametrize("schedule", [capi.WS_TWO_TEMP, capi.WS_OVERWRITE, capi.WS_READONLY_INPLACE,
+                                      capi.WS_OVR, capi.WS_ACCR, capi.WS_BLOCKED, capi.WS_BLOCKED_ACC,
+                                      capi.WS_OVL, capi.WS_ACR, capi.WS_IPMM_ACC])
+@pytest.mark.parametrize("shape", [(0, 5, 7), (6, 0, 7), (6, 5, 0)])
+def test_empty_products(schedule, shape):
+    m, k, n = shape
+    p = 65521
+    beta = 0 if schedule in (capi.WS_READONLY_INPLACE, capi.WS_OVR, capi.WS_OVL,
+                             capi.WS_IPMM_ACC) else 7
+    A, B, C = inputs.uniform(43, m, k, n, p, with_c=True)
+    st, C2, _, _ = call(schedule, A, B, C, 3, beta, p, 2)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, 3, beta, p))
+
+
 def test_attached_workspace_exact_size_and_no_hidden_allocation():
     t = __import__("torch")
     p = 65521

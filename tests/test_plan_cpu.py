@@ -183,6 +183,25 @@ def test_overwrite_family_argument_errors():
     assert status(64, 64, 64, capi.WS_IPMM_ACC, 2, 3) == capi.WS_ESCHEDULE
 
 
+ALL_SELECTORS = [capi.WS_CLASSICAL, capi.WS_TWO_TEMP, capi.WS_OVERWRITE, capi.WS_READONLY_INPLACE,
+                 capi.WS_HL_THREE_TEMP, capi.WS_OVR, capi.WS_ACCR, capi.WS_BLOCKED,
+                 capi.WS_BLOCKED_ACC, capi.WS_OVL, capi.WS_ACR, capi.WS_IPMM_ACC]
+BETA_FREE = (capi.WS_READONLY_INPLACE, capi.WS_OVR, capi.WS_OVL, capi.WS_IPMM_ACC)
+
+
+@pytest.mark.parametrize("schedule", ALL_SELECTORS)
+@pytest.mark.parametrize("shape", [(0, 5, 7), (6, 0, 7), (6, 5, 0), (0, 0, 0)])
+def test_empty_products_under_every_schedule(schedule, shape):
+    """m = 0 or n = 0 leaves C alone and k = 0 gives C <- beta*C, whatever the
+    schedule (the shape restrictions of the tables do not apply)."""
+    m, k, n = shape
+    p = 65521
+    beta = 0 if schedule in BETA_FREE else 7
+    (A, B, C), (A2, B2, C2), info = _interp(schedule, m, k, n, p, 3, beta, 2, seed=5)
+    assert info.workspace_bytes == 0
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, 3, beta, p))
+
+
 def test_blocked_workload_bytes():
     """The accumulating 4096^3 product with three levels: t = 2 needs a
     quarter (Table 2) or a sixth (Table 9) of n^2 entries at most."""
