@@ -55,7 +55,9 @@ SCHEDULE_NAMES = {0: "classical", 1: "two temporaries (Table 1 / Table 9)",
                   3: "read-only in place (Algorithm 2)", 4: "three temporaries (Table 2)",
                   6: "overwrite, accumulate right (Table 5)", 7: "accumulate right (Table 7)",
                   8: "blocked accumulation over Table 2 (Section 7.2)",
-                  9: "blocked accumulation over Table 9 (Section 7.2)"}
+                  9: "blocked accumulation over Table 9 (Section 7.2)",
+                  10: "overwrite left (Table 4)", 11: "accumulate, overwrite B, rectangular (Table 8)",
+                  12: "read-only in place with Table 9 accumulations (Algorithm 2)"}
 WORKLOADS = ("acc_4096_p65521_l3", "t1_512_p65521_l1_i64", "ipmm_8192x4096x8192_p8388593",
              "t1_16384_p1048573", "overwrite_8192x16384x8192_p8388593", "acc_4096_p65521_blocked",
              "batch_2000")

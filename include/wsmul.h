@@ -180,9 +180,9 @@ WSMUL_API int wsmul_mod_p_ex(const ws_args *args);
 
 /*
  * Bytes of temporaries the schedule needs (its "extra memory": Eq. (1) for
- * Table 1, Eq. (2) for Table 2, the bounds of Sections 5-6 for Tables 5-9,
- * zero for Table 3 and Algorithm 2, one (n/t)-block call for Section 7.2 with
- * t = 2), for dense binary64 or int64 storage.
+ * Table 1, Eq. (2) for Table 2, the bounds of Sections 5-6 for Tables 4-9,
+ * zero for Table 3 and Algorithms 1 and 2, one (n/t)-block call for
+ * Section 7.2 with t = 2), for dense binary64 or int64 storage.
  * Returns 0 for unsupported combinations (check wsmul_last_error()).
  */
 WSMUL_API size_t wsmul_workspace_bytes(int64_t m, int64_t k, int64_t n, int dtype, int schedule,

@@ -269,9 +269,10 @@ class Emitter {
     };
     // Temporaries of one call at call depth d.  Normally they are carved from
     // the workspace slot of that depth (calls at one depth never overlap in
-    // time); inside Algorithm 2 they are quadrants of the lent C region:
-    // first in the top-left, second in the bottom-left, third in the
-    // top-right, and the bottom-right is lent on to the callees.
+    // time); inside Algorithms 1 and 2 they are quadrants of a lent region
+    // (a free square of C or A): first in the top-left, second in the
+    // bottom-left, third in the top-right, and the bottom-right is lent on to
+    // the callees.
     Frame frame(int d, std::initializer_list<std::pair<int64_t, int64_t>> shapes) {
         Frame f;
         if (!regions_.empty()) {
