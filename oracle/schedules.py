@@ -103,10 +103,13 @@ def fp64_chunk(p: int) -> int:
 class Winograd:
     """One replay: state (counters, arena) plus one method per schedule."""
 
-    def __init__(self, p, *, dry=False, garbage_seed=None, kc=None):
+    def __init__(self, p, *, dry=False, garbage_seed=None, kc=None, junk=None):
         self.p = int(p)
         self.dry = dry
         self.rng = None if garbage_seed is None else np.random.default_rng(garbage_seed)
+        # Symbolic replays: ``junk()`` returns a fresh unknown value; then every
+        # matrix is an object array and dead values are junk, not residues.
+        self.junk = junk
         self.kc = int(kc) if kc else fp64_chunk(self.p)
         self.adds = 0            # element additions, one per element per addition row
         self.leaf_ops = 0        # classical base-case operations
@@ -120,7 +123,10 @@ class Winograd:
 
     # ---------------------------------------------------------------- storage
     def _garbage(self, V):
-        if self.rng is not None and not self.dry and V.size:
+        if self.junk is not None and V.size:
+            for idx in np.ndindex(V.shape):
+                V[idx] = self.junk()
+        elif self.rng is not None and not self.dry and V.size:
             V[...] = self.rng.integers(0, self.p, size=V.shape, dtype=np.int64)
 
     @contextmanager
@@ -153,7 +159,7 @@ class Winograd:
                 V = np.lib.stride_tricks.as_strided(np.zeros(1, np.int64),
                                                     shape=(r, c), strides=(0, 0))
             else:
-                V = np.zeros((r, c), dtype=np.int64)
+                V = np.zeros((r, c), dtype=object if self.junk else np.int64)
                 self._garbage(V)
             views.append(V)
             total += r * c
@@ -203,7 +209,8 @@ class Winograd:
         for l0 in range(0, k, self.kc):
             s = s + A[:, l0:l0 + self.kc] @ B[l0:l0 + self.kc, :]
             if s.size:
-                self.max_partial = max(self.max_partial, int(np.abs(s).max()))
+                if s.dtype != object:
+                    self.max_partial = max(self.max_partial, int(np.abs(s).max()))
             s %= p
         r = (int(a) % p) * s % p
         if int(b) % p:
