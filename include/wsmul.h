@@ -242,7 +242,11 @@ WSMUL_API int wsmul_graph_destroy(void *graph_exec);
  * whose temporaries fit mem_budget is expanded into its fused plan and costed
  * with per-kernel rates measured on MI355X (base products by tile class and
  * base kind, addition groups by bytes moved, a floor per launch).  Fills
- * choice->schedule, ->levels, ->base; other fields are left as passed.
+ * choice->schedule, ->levels, ->base and ->blocks (t of the blocked
+ * accumulation, a candidate for accumulating products when the budget is
+ * below the unblocked schedules' temporaries); other fields are left as
+ * passed.  choice->beta says whether the product accumulates; a fixed
+ * choice->schedule, ->levels, ->base or ->blocks is kept.
  * Decisions are cached in memory and, when WSMUL_TUNE_CACHE names a file, in
  * that file (one JSON object per line). */
 WSMUL_API int wsmul_autotune(int64_t m, int64_t k, int64_t n, int64_t p, int dtype,
