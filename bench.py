@@ -178,7 +178,14 @@ class Ctx:
                     "bytes_per_launch": add_bytes_per}
         counts = {"base_products": int(tr.gemm_launches // ntraced),
                   "addition_groups": int(tr.add_launches // ntraced)}
-        return roof, per_step, counts
+        add_roof = None
+        if tr.add_launches:
+            gbs = add_bytes_per / (add_avg_ms * 1e-3) / 1e9
+            add_roof = {"bound": "hbm", "kernel": "fused addition rows", "achieved": round(gbs, 1),
+                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                        "traffic": measured_traffic(self.args.workload, False),
+                        "avg_launch_ms": round(add_avg_ms, 5), "bytes_per_launch": add_bytes_per}
+        return roof, per_step, counts, add_roof
 
 
 def cpu_baseline_rows(A, B, C, alpha, beta, p, budget_s=12.0):
@@ -317,7 +324,9 @@ def single_product(ctx, name):
     value = flops / (ms_step * 1e-3) / 1e9
     log("%s: %.3f ms/step, %.1f Gop/s, temporaries %d B" % (name, ms_step, value,
                                                            stats.workspace_bytes))
-    roof, per_step, counts = ctx.traced(head, max(1, min(steps, 5)), int8_ops=int8)
+    roof, per_step, counts, add_roof = ctx.traced(head, max(1, min(steps, 5)), int8_ops=int8)
+    if add_roof is not None and roof["bound"] != "hbm":
+        extra["roofline_additions"] = add_roof
     extra["peak_temp_bytes"] = int(stats.workspace_bytes)
     extra["launches_per_step"] = counts
     extra["kernel_time_per_step_ms"] = per_step
