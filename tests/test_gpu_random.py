@@ -1,6 +1,6 @@
 """GPU parity on a seeded random sweep: every schedule selector, random shapes
 (ragged ones where the schedule peels), depths, moduli, alpha and beta, both
-storage types.  The product is compared with oracle O1 element by element, and
+storage types and, where its bounds allow, the 8-bit digit base.  The product is compared with oracle O1 element by element, and
 the inputs an overwriting schedule leaves behind with oracle O2's replay."""
 import numpy as np
 import pytest
@@ -79,10 +79,12 @@ def test_random_case(case):
     sched, m, k, n, L, beta, t, p, name, i = case
     rng = np.random.default_rng([78, i])
     dtype = capi.WS_I64 if i % 3 == 0 else capi.WS_F64
+    base = (capi.WS_BASE_I8_LIMBS if i % 4 == 1 and p <= 16711423 and k <= 32768
+            else capi.WS_BASE_F64_MFMA)
     alpha = int(rng.integers(-(1 << 40), 1 << 40))
-    print("random case", i, sched, (m, k, n), L, beta, t, p, dtype, flush=True)
+    print("random case", i, sched, (m, k, n), L, beta, t, p, dtype, base, flush=True)
     A, B, C = inputs.uniform(900 + i, m, k, n, p, with_c=True)
-    st, C2, A2, B2 = call(sched, A, B, C, alpha, beta, p, L, dtype=dtype, blocks=t)
+    st, C2, A2, B2 = call(sched, A, B, C, alpha, beta, p, L, dtype=dtype, base=base, blocks=t)
     assert st == capi.WS_OK, capi.wsmul_last_error()
     assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, alpha, beta, p))
     if name is not None:
