@@ -135,10 +135,14 @@ void save_entry(const Key &k, const Choice &c) {
     std::fclose(f);
 }
 
-// Search every admissible candidate; returns false if none fits.
-bool search(const Key &key, Choice &best) {
-    bool found = false;
+// Search every admissible candidate; returns false if none fits.  When no
+// candidate passes the schedule's own checks, *reject holds the status and
+// message of the last check (WS_OK when some candidate only missed the
+// memory budget).
+bool search(const Key &key, Choice &best, Resolved *reject) {
+    bool found = false, admissible = false;
     best.cost_us = 1e300;
+    reject->status = WS_OK;
     // (schedule, t) pairs; t only matters for the blocked schedules.
     std::vector<std::pair<int, int>> cands;
     if (key.schedule != WS_AUTO) {
@@ -178,11 +182,19 @@ bool search(const Key &key, Choice &best) {
         while (top < 5 && (mb >> (top + 1)) >= 64)
             ++top;
         const int lo = key.levels >= 0 ? key.levels : (sched == WS_CLASSICAL ? 0 : 1);
-        const int hi = key.levels >= 0 ? key.levels : (sched == WS_CLASSICAL ? 0 : top);
+        int hi = key.levels >= 0 ? key.levels : (sched == WS_CLASSICAL ? 0 : top);
+        if (key.schedule != WS_AUTO)
+            hi = std::max(hi, lo);   // a schedule the caller fixed gets at least one depth
+
         for (int l = lo; l <= hi; ++l) {
             const Resolved r = resolve_schedule(sched, key.m, key.k, key.n, key.beta_nz != 0, l, t);
-            if (r.status != WS_OK)
+            if (r.status != WS_OK) {
+                if (!admissible)
+                    *reject = r;
                 continue;
+            }
+            admissible = true;
+            reject->status = WS_OK;
             PlanKey pk{};
             pk.m = key.m;
             pk.k = key.k;
@@ -296,7 +308,12 @@ extern "C" int wsmul_autotune(int64_t m, int64_t k, int64_t n, int64_t p, int dt
             return WS_OK;
         }
     }
-    if (!search(key, best)) {
+    Resolved reject;
+    if (!search(key, best, &reject)) {
+        if (reject.status != WS_OK) {
+            set_error(reject.error);
+            return reject.status;
+        }
         set_error("wsmul_autotune: no schedule fits the memory budget at this shape");
         return WS_ENOMEM;
     }

@@ -115,6 +115,18 @@ def test_bad_arguments():
     assert _choice(64, 64, 64, 65521, schedule=99)[0] == capi.WS_ESCHEDULE
 
 
+def test_fixed_schedule_errors_are_the_schedules_own():
+    """With the schedule fixed, a request the schedule cannot take fails with
+    that schedule's status, not with a memory-budget error."""
+    assert _choice(64, 64, 64, 65521, beta=1, schedule=capi.WS_READONLY_INPLACE,
+                   levels=1)[0] == capi.WS_ESCHEDULE
+    assert _choice(64, 64, 48, 65521, schedule=capi.WS_OVL)[0] == capi.WS_ESHAPE
+    st, sched, lev, _ = _choice(48, 48, 48, 65521, schedule=capi.WS_OVL)
+    assert (st, sched) == (capi.WS_OK, capi.WS_OVL) and lev >= 1
+    assert _choice(4096, 4096, 4096, 65521, beta=1, budget=1000, schedule=capi.WS_TWO_TEMP,
+                   levels=3)[0] == capi.WS_ENOMEM
+
+
 def test_cache_file_round_trip(tmp_path):
     """A fresh process writes its choices to WSMUL_TUNE_CACHE; a second one
     reads them back (the file holds one JSON object per line)."""
