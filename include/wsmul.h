@@ -253,6 +253,35 @@ WSMUL_API int wsmul_autotune(int64_t m, int64_t k, int64_t n, int64_t p, int dty
                              size_t mem_budget, ws_args *choice);
 
 /* ------------------------------------------------------------------------
+ * Tile choice of the binary64 base products.  By default a product's kernel
+ * follows a fixed rule by shape (the larger tiles for the larger products).
+ * wsmul_tune_tiles times every kernel kind that can take an m x k by k x n
+ * product mod p on the current device (dense operands it allocates itself,
+ * `reps` timed launches each after one warm-up) and remembers the fastest
+ * for that (m, k, n, p, dtype) in this process; later base products of that
+ * shape use it wherever their views allow.  times_us (NULL or WS_TILE_KINDS
+ * entries) receives the average time per launch, -1 for kinds that cannot
+ * take the shape; *best (may be NULL) the kind kept.  The call synchronises.
+ * wsmul_set_tile pins a kind for a shape instead (-1 restores the rule);
+ * wsmul_tune_plan tunes every distinct base-product shape of the plan of
+ * `args` (binary64 base; no-op for the 8-bit digit base).  The choice never
+ * changes a result: every kind computes the same exact product.
+ */
+enum {
+    WS_TILE_BIG128 = 0,  /* 128 x 128, operands loaded straight into LDS, pipelined  */
+    WS_TILE_LDS128 = 1,  /* 128 x 128, staged through registers (any shape)          */
+    WS_TILE_DMA64 = 2,   /* 64 x 64, straight into LDS, inner dimension split by wave */
+    WS_TILE_LDS64 = 3,   /* 64 x 64, staged through registers (any shape)            */
+    WS_TILE_DMA32 = 4,   /* 32 x 32, straight into LDS, inner dimension split by wave */
+    WS_TILE_SK32 = 5,    /* 32 x 32, from global memory, inner dimension split (any)  */
+    WS_TILE_KINDS = 6
+};
+WSMUL_API int wsmul_tune_tiles(int64_t m, int64_t k, int64_t n, int64_t p, int dtype, int reps,
+                               int *best, double *times_us);
+WSMUL_API int wsmul_set_tile(int64_t m, int64_t k, int64_t n, int64_t p, int dtype, int kind);
+WSMUL_API int wsmul_tune_plan(const ws_args *args, int reps);
+
+/* ------------------------------------------------------------------------
  * Plan introspection (host only, no GPU needed).
  *
  * A plan is the schedule expanded to `levels`: a list of operations on views

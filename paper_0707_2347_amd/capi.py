@@ -20,6 +20,9 @@ WS_OK, WS_EINVAL, WS_ESHAPE, WS_EMODULUS, WS_ERANGE, WS_ESCHEDULE, WS_ENOMEM, WS
 WS_F64, WS_I64 = 0, 1
 WS_BASE_AUTO, WS_BASE_F64_MFMA, WS_BASE_I8_LIMBS = 0, 1, 2
 WS_FLAG_CHECK, WS_FLAG_NOFUSE, WS_FLAG_TRACE, WS_FLAG_SYNC = 1, 2, 4, 8
+(WS_TILE_BIG128, WS_TILE_LDS128, WS_TILE_DMA64, WS_TILE_LDS64, WS_TILE_DMA32,
+ WS_TILE_SK32) = range(6)
+WS_TILE_KINDS = 6
 WS_MAX_IN, WS_MAX_OUT = 8, 6
 WS_BUF_A, WS_BUF_B, WS_BUF_C, WS_BUF_W = 0, 1, 2, 3
 WS_OP_ADD, WS_OP_GEMM = 0, 1
@@ -80,6 +83,14 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libwsmul.so is not built: run __graft_entry__.build() "
                                "(no other implementation exists)")
+        # The torch wheel ships its own HIP runtime.  Load it before the
+        # library so that both bind to that one runtime (the one that owns the
+        # tensors and streams passed in); opened first, the library would bring
+        # the system runtime in beside it and find no device for its launches.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         sig = {
             "wsmul_mod_p": (ctypes.c_int, [_i64, _i64, _i64, _i64, _vp, _vp, _vp, _i64, _i64,
@@ -114,6 +125,11 @@ def lib():
             "wsmul_graph_destroy": (ctypes.c_int, [_vp]),
             "wsmul_autotune": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int,
                                               ctypes.c_size_t, ctypes.POINTER(ws_args)]),
+            "wsmul_tune_tiles": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int,
+                                                ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(_dbl)]),
+            "wsmul_set_tile": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int]),
+            "wsmul_tune_plan": (ctypes.c_int, [ctypes.POINTER(ws_args), ctypes.c_int]),
         })
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -266,3 +282,19 @@ def wsmul_autotune(m, k, n, p, dtype=WS_F64, mem_budget=(1 << 64) - 1, schedule=
     c.schedule, c.levels, c.base, c.beta, c.blocks = schedule, levels, base, beta, blocks
     st = lib().wsmul_autotune(m, k, n, p, dtype, mem_budget, ctypes.byref(c))
     return st, c.schedule, c.levels, c.base, c.blocks
+
+
+def wsmul_tune_tiles(m, k, n, p, dtype=WS_F64, reps=5):
+    """Return (status, kind kept, per-kind microseconds) for one product shape."""
+    best = ctypes.c_int(-1)
+    times = (_dbl * WS_TILE_KINDS)()
+    st = lib().wsmul_tune_tiles(m, k, n, p, dtype, reps, ctypes.byref(best), times)
+    return st, best.value, list(times)
+
+
+def wsmul_set_tile(m, k, n, p, dtype, kind):
+    return lib().wsmul_set_tile(m, k, n, p, dtype, kind)
+
+
+def wsmul_tune_plan(args, reps=5):
+    return lib().wsmul_tune_plan(ctypes.byref(args), reps)

@@ -5,7 +5,9 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -379,6 +381,66 @@ size_t wsmul_workspace_bytes(int64_t m, int64_t k, int64_t n, int dtype, int sch
         set_error(e.what());
         return 0;
     }
+}
+
+int wsmul_tune_tiles(int64_t m, int64_t k, int64_t n, int64_t p, int dtype, int reps, int *best,
+                     double *times_us) {
+    if (m <= 0 || k <= 0 || n <= 0 || (dtype != WS_F64 && dtype != WS_I64) || reps < 1 ||
+        reps > 10000)
+        return fail(WS_EINVAL, "wsmul_tune_tiles: bad shape, dtype or repetition count");
+    if (p < 2 || p >= (int64_t(1) << 24))
+        return fail(WS_EMODULUS, "p must lie in [2, 2^24)");
+    double us[TILE_KINDS];
+    const hipError_t e = time_tiles(m, n, k, p, dtype, reps, us);
+    if (e != hipSuccess)
+        return fail(WS_EHIP, std::string("wsmul_tune_tiles: ") + hipGetErrorString(e));
+    int kind = -1;
+    for (int t = 0; t < TILE_KINDS; ++t)
+        if (us[t] >= 0.0 && (kind < 0 || us[t] < us[kind]))
+            kind = t;
+    choose_tile(m, n, k, p, dtype, kind);
+    if (best)
+        *best = kind;
+    if (times_us)
+        for (int t = 0; t < TILE_KINDS; ++t)
+            times_us[t] = us[t];
+    return WS_OK;
+}
+
+int wsmul_set_tile(int64_t m, int64_t k, int64_t n, int64_t p, int dtype, int kind) {
+    if (m < 0 || k < 0 || n < 0 || (dtype != WS_F64 && dtype != WS_I64) || kind < -1 ||
+        kind >= TILE_KINDS)
+        return fail(WS_EINVAL, "wsmul_set_tile: bad shape, dtype or kind");
+    choose_tile(m, n, k, p, dtype, kind);
+    return WS_OK;
+}
+
+int wsmul_tune_plan(const ws_args *args, int reps) {
+    ws_args a;
+    PlanKey key;
+    Resolved res;
+    int rc = prepare(args, a, key, res);
+    if (rc != WS_OK)
+        return rc;
+    if (a.m == 0 || a.n == 0 || a.base == WS_BASE_I8_LIMBS)
+        return WS_OK;
+    std::shared_ptr<Plan> plan;
+    try {
+        plan = get_plan(key);
+    } catch (const std::exception &e) {
+        return fail(WS_EINVAL, std::string("planner: ") + e.what());
+    }
+    std::set<std::tuple<int64_t, int64_t, int64_t>> shapes;
+    for (const OpDesc &op : plan->ops)
+        if (op.kind == WS_OP_GEMM && op.a.rows > 0 && op.a.cols > 0 && op.b.cols > 0)
+            shapes.insert(std::make_tuple(op.a.rows, op.a.cols, op.b.cols));
+    for (const auto &sh : shapes) {
+        rc = wsmul_tune_tiles(std::get<0>(sh), std::get<1>(sh), std::get<2>(sh), a.p, a.dtype,
+                              reps, nullptr, nullptr);
+        if (rc != WS_OK)
+            return rc;
+    }
+    return WS_OK;
 }
 
 int wsmul_plan_info(const ws_args *args, ws_stats *stats) {

@@ -3,8 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "device.hpp"
 #include "gemm_common.hpp"
@@ -919,15 +923,58 @@ static int32_t fold_tiles(int64_t p, bool centre, int64_t K) {
     return (int32_t)std::max(1.0, std::min(t, 1.0e9));
 }
 
-template <typename T>
-static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
+// Kinds of binary64 base-product kernels (TILE_* in kernels.hpp).  A kind
+// is admissible for a product when the kernel's shape and alignment
+// assumptions hold; the default choice is a fixed rule by tile counts, and a
+// kind measured faster for the shape (wsmul_tune_tiles) or pinned by the
+// caller (wsmul_set_tile) replaces it when admissible.
+static bool dma_aligned(const GemmParams &P) {
+    return P.lda % 2 == 0 && P.ldb % 2 == 0 && aligned16(P.A) && aligned16(P.B);
+}
+
+static bool tile_admissible(int kind, const GemmParams &P) {
+    switch (kind) {
+    case TILE_BIG128:
+        return WS_BIG_ENABLE && P.M % 128 == 0 && P.N % 128 == 0 && P.K % 16 == 0 && P.K > 0 &&
+               dma_aligned(P);
+    case TILE_DMA64:
+        return P.M % 64 == 0 && P.N % 64 == 0 && P.K % 64 == 0 && P.K > 0 && dma_aligned(P);
+    case TILE_DMA32:
+        return P.M % 32 == 0 && P.N % 32 == 0 && P.K % 64 == 0 && P.K > 0 && dma_aligned(P);
+    case TILE_LDS128:
+    case TILE_LDS64:
+    case TILE_SK32:
+        return true;
+    default:
+        return false;
+    }
+}
+
+static int default_tile(const GemmParams &P) {
+    if (P.K == 0)
+        return TILE_SK32;   // C <- beta*C only
     const int64_t big = ((P.M + 127) / 128) * ((P.N + 127) / 128);
     const int64_t mid = ((P.M + 63) / 64) * ((P.N + 63) / 64);
+    if (big >= 256 && tile_admissible(TILE_BIG128, P))
+        return TILE_BIG128;
+    if (big >= 512)
+        return TILE_LDS128;
+    if (mid >= 256 && tile_admissible(TILE_DMA64, P))
+        return TILE_DMA64;
+    if (mid >= 256)
+        return TILE_LDS64;
+    if (tile_admissible(TILE_DMA32, P))
+        return TILE_DMA32;
+    return TILE_SK32;
+}
+
+template <typename T>
+static hipError_t launch_tile(int kind, GemmParams &P, bool vec2, hipStream_t s) {
     const bool centre = fold_tiles((int64_t)P.p, false, P.K) != 0;
     P.kc_tiles = fold_tiles((int64_t)P.p, centre, P.K);
     P.half = std::floor(P.p / 2.0);
-    if (WS_BIG_ENABLE && big >= 256 && P.M % 128 == 0 && P.N % 128 == 0 && P.K % 16 == 0 &&
-        P.K > 0 && P.lda % 2 == 0 && P.ldb % 2 == 0 && aligned16(P.A) && aligned16(P.B)) {
+    switch (kind) {
+    case TILE_BIG128: {
         // Centre only when uncentred folds (a reduction of 32 accumulators
         // per lane) would cost more than centring 24 operands per K-step.
         const int32_t t_nc = fold_chunks((int64_t)P.p, false, P.K, 1, 16);
@@ -935,13 +982,15 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
         P.kc_tiles = fold_chunks((int64_t)P.p, c2, P.K, 1, 16);
         P.tiles_m = (int32_t)(P.M / 128);
         P.tiles_n = (int32_t)(P.N / 128);
-        const dim3 grid((uint32_t)big), block(512);
+        const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(512);
         if (c2) ws_launch((gemm_big_kernel<T, true>), grid, block, 0, s, P);
         else ws_launch((gemm_big_kernel<T, false>), grid, block, 0, s, P);
-    } else if (big >= 512) {
+        break;
+    }
+    case TILE_LDS128: {
         P.tiles_m = (int32_t)((P.M + 127) / 128);
         P.tiles_n = (int32_t)((P.N + 127) / 128);
-        const dim3 grid((uint32_t)big), block(256);
+        const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(256);
         if (centre) {
             if (vec2) ws_launch((gemm_lds_kernel<T, 128, 128, true, true>), grid, block, 0, s, P);
             else ws_launch((gemm_lds_kernel<T, 128, 128, true, false>), grid, block, 0, s, P);
@@ -949,8 +998,9 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
             if (vec2) ws_launch((gemm_lds_kernel<T, 128, 128, false, true>), grid, block, 0, s, P);
             else ws_launch((gemm_lds_kernel<T, 128, 128, false, false>), grid, block, 0, s, P);
         }
-    } else if (mid >= 256 && P.M % 64 == 0 && P.N % 64 == 0 && P.K % 64 == 0 && P.lda % 2 == 0 &&
-               P.ldb % 2 == 0 && aligned16(P.A) && aligned16(P.B)) {
+        break;
+    }
+    case TILE_DMA64: {
         constexpr int W = WS_DMA64_WAVES, ST = WS_DMA64_STAGES, SK = WS_DMA64_SK;
         const bool c2 = dma_centre((int64_t)P.p, P.K, 64, W, SK);
         P.kc_tiles = fold_chunks((int64_t)P.p, c2, P.K, W, SK);
@@ -959,10 +1009,12 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
         const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(64 * W);
         if (c2) ws_launch((gemm_dma_kernel<T, true, 64, W, ST, SK>), grid, block, 0, s, P);
         else ws_launch((gemm_dma_kernel<T, false, 64, W, ST, SK>), grid, block, 0, s, P);
-    } else if (mid >= 256) {
+        break;
+    }
+    case TILE_LDS64: {
         P.tiles_m = (int32_t)((P.M + 63) / 64);
         P.tiles_n = (int32_t)((P.N + 63) / 64);
-        const dim3 grid((uint32_t)mid), block(256);
+        const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(256);
         if (centre) {
             if (vec2) ws_launch((gemm_lds_kernel<T, 64, 64, true, true>), grid, block, 0, s, P);
             else ws_launch((gemm_lds_kernel<T, 64, 64, true, false>), grid, block, 0, s, P);
@@ -970,8 +1022,9 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
             if (vec2) ws_launch((gemm_lds_kernel<T, 64, 64, false, true>), grid, block, 0, s, P);
             else ws_launch((gemm_lds_kernel<T, 64, 64, false, false>), grid, block, 0, s, P);
         }
-    } else if (P.M % 32 == 0 && P.N % 32 == 0 && P.K % 64 == 0 && P.K > 0 && P.lda % 2 == 0 &&
-               P.ldb % 2 == 0 && aligned16(P.A) && aligned16(P.B)) {
+        break;
+    }
+    case TILE_DMA32: {
         constexpr int W = WS_DMA_WAVES, ST = WS_DMA_STAGES, SK = WS_DMA_SK;
         const bool c2 = dma_centre((int64_t)P.p, P.K, 32, W, SK);
         P.kc_tiles = fold_chunks((int64_t)P.p, c2, P.K, W, SK);
@@ -980,7 +1033,9 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
         const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(64 * W);
         if (c2) ws_launch((gemm_dma_kernel<T, true, 32, W, ST, SK>), grid, block, 0, s, P);
         else ws_launch((gemm_dma_kernel<T, false, 32, W, ST, SK>), grid, block, 0, s, P);
-    } else {
+        break;
+    }
+    default: {
         P.tiles_m = (int32_t)((P.M + 31) / 32);
         P.tiles_n = (int32_t)((P.N + 31) / 32);
         const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(64 * WS_SK_WAVES);
@@ -993,7 +1048,124 @@ static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s) {
             else ws_launch((gemm_sk_kernel<T, false, false, WS_SK_WAVES>), grid, block, 0, s, P);
         }
     }
+    }
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_gemm_t(GemmParams &P, bool vec2, hipStream_t s, int dtype) {
+    int kind = default_tile(P);
+    const int chosen = chosen_tile(P.M, P.N, P.K, (int64_t)P.p, dtype);
+    if (chosen >= 0 && P.K > 0 && tile_admissible(chosen, P))
+        kind = chosen;
+    return launch_tile<T>(kind, P, vec2, s);
+}
+
+// ------------------------------------------------------- tile choices
+namespace {
+using TileKey = std::tuple<int64_t, int64_t, int64_t, int64_t, int>;
+std::mutex g_tile_mu;
+std::map<TileKey, int> g_tiles;
+std::atomic<bool> g_tiles_any{false};
+}  // namespace
+
+int chosen_tile(int64_t M, int64_t N, int64_t K, int64_t p, int dtype) {
+    if (!g_tiles_any.load(std::memory_order_acquire))
+        return -1;
+    std::lock_guard<std::mutex> lock(g_tile_mu);
+    auto it = g_tiles.find(TileKey{M, N, K, p, dtype});
+    return it == g_tiles.end() ? -1 : it->second;
+}
+
+void choose_tile(int64_t M, int64_t N, int64_t K, int64_t p, int dtype, int kind) {
+    std::lock_guard<std::mutex> lock(g_tile_mu);
+    if (kind < 0)
+        g_tiles.erase(TileKey{M, N, K, p, dtype});
+    else
+        g_tiles[TileKey{M, N, K, p, dtype}] = kind;
+    g_tiles_any.store(!g_tiles.empty(), std::memory_order_release);
+}
+
+template <typename T>
+static hipError_t time_tiles_t(const GemmParams &base, bool vec2, int reps, hipStream_t s,
+                               double *us) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess)
+        e = hipEventCreate(&e1);
+    for (int kind = 0; kind < TILE_KINDS && e == hipSuccess; ++kind) {
+        if (!tile_admissible(kind, base))
+            continue;
+        GemmParams P = base;
+        e = launch_tile<T>(kind, P, vec2, s);            // warm-up
+        if (e == hipSuccess)
+            e = hipEventRecord(e0, s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) {
+            P = base;
+            e = launch_tile<T>(kind, P, vec2, s);
+        }
+        if (e == hipSuccess)
+            e = hipEventRecord(e1, s);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess)
+            us[kind] = 1000.0 * (double)ms / (double)reps;
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    return e;
+}
+
+hipError_t time_tiles(int64_t M, int64_t N, int64_t K, int64_t p, int dtype, int reps,
+                      double *us) {
+    for (int k = 0; k < TILE_KINDS; ++k)
+        us[k] = -1.0;
+    const size_t esz = 8;
+    void *A = nullptr, *B = nullptr, *C = nullptr;
+    hipStream_t s = nullptr;
+    hipError_t e = hipMalloc(&A, std::max<size_t>(1, (size_t)(M * K) * esz));
+    if (e == hipSuccess)
+        e = hipMalloc(&B, std::max<size_t>(1, (size_t)(K * N) * esz));
+    if (e == hipSuccess)
+        e = hipMalloc(&C, std::max<size_t>(1, (size_t)(M * N) * esz));
+    if (e == hipSuccess)   // zeros are residues in both storage types
+        e = hipMemset(A, 0, (size_t)(M * K) * esz);
+    if (e == hipSuccess)
+        e = hipMemset(B, 0, (size_t)(K * N) * esz);
+    if (e == hipSuccess)
+        e = hipStreamCreate(&s);
+    if (e == hipSuccess) {
+        GemmParams P{};
+        P.A = A;
+        P.B = B;
+        P.lda = K;
+        P.ldb = N;
+        P.M = M;
+        P.N = N;
+        P.K = K;
+        P.p = (double)p;
+        P.pinv = 1.0 / (double)p;
+        P.alpha = 1.0;
+        P.nin = 1;
+        P.nout = 1;
+        P.eout[0] = C;
+        P.eldo[0] = N;
+        P.coef[0][0] = 1.0;
+        const bool vec2 = K % 2 == 0 && N % 2 == 0;
+        e = dtype == WS_I64 ? time_tiles_t<int64_t>(P, vec2, std::max(reps, 1), s, us)
+                            : time_tiles_t<double>(P, vec2, std::max(reps, 1), s, us);
+    }
+    if (s)
+        (void)hipStreamSynchronize(s), (void)hipStreamDestroy(s);
+    (void)hipFree(A);
+    (void)hipFree(B);
+    (void)hipFree(C);
+    return e;
 }
 
 hipError_t launch_gemm(const ws_op_desc &op, const DevBufs &bufs, int dtype, int64_t p,
@@ -1029,8 +1201,8 @@ hipError_t launch_gemm(const ws_op_desc &op, const DevBufs &bufs, int dtype, int
                       aligned16(P.A) && aligned16(P.B);
     if ((M + 31) / 32 * ((N + 31) / 32) >= (int64_t(1) << 31))
         return hipErrorInvalidValue;
-    return dtype == WS_I64 ? launch_gemm_t<int64_t>(P, vec2, stream)
-                           : launch_gemm_t<double>(P, vec2, stream);
+    return dtype == WS_I64 ? launch_gemm_t<int64_t>(P, vec2, stream, dtype)
+                           : launch_gemm_t<double>(P, vec2, stream, dtype);
 }
 
 }  // namespace wsmul

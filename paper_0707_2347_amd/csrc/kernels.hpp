@@ -42,6 +42,23 @@ struct DevBufs {
 hipError_t launch_add(const ws_op_desc &op, const DevBufs &bufs, int dtype, int64_t p,
                       hipStream_t stream);
 
+// Kinds of binary64 base-product kernels (the values of WS_TILE_* in the
+// header): 128 x 128 tiles pipelined through LDS by direct loads, or staged
+// through registers; 64 x 64 tiles by direct loads with split inner
+// dimension, or register-staged; 32 x 32 tiles by direct loads with split
+// inner dimension, or straight from global memory.
+enum : int {
+    TILE_BIG128 = 0, TILE_LDS128 = 1, TILE_DMA64 = 2, TILE_LDS64 = 3, TILE_DMA32 = 4,
+    TILE_SK32 = 5, TILE_KINDS = 6
+};
+// Kind chosen for products of this shape and modulus (measured or pinned),
+// or -1 for the default rule.  choose_tile with kind -1 forgets the choice.
+int chosen_tile(int64_t M, int64_t N, int64_t K, int64_t p, int dtype);
+void choose_tile(int64_t M, int64_t N, int64_t K, int64_t p, int dtype, int kind);
+// Time every admissible kind on a dense M x K by K x N product mod p on the
+// current device (us[kind] in microseconds, -1 when not admissible).
+hipError_t time_tiles(int64_t M, int64_t N, int64_t K, int64_t p, int dtype, int reps, double *us);
+
 // One base product with its epilogue group (binary64 matrix cores).
 hipError_t launch_gemm(const ws_op_desc &op, const DevBufs &bufs, int dtype, int64_t p,
                        hipStream_t stream);
