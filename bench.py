@@ -328,6 +328,19 @@ def single_product(ctx, name):
     if add_roof is not None and roof["bound"] != "hbm":
         extra["roofline_additions"] = add_roof
     extra["peak_temp_bytes"] = int(stats.workspace_bytes)
+    if nbytes > 0:
+        # Device-measured temporaries: one more call on a workspace filled,
+        # with a guard band behind it, by a value that is not a residue.
+        guard = 4096
+        wsg = torch.full((nbytes // 8 + guard,), -7, dtype=dA.dtype, device=ctx.dev)
+        if overwrites:
+            restore()
+        run(mkargs(sched, lev, base, wsg, nbytes, blocks))
+        torch.cuda.synchronize()
+        w = wsg.cpu().numpy()
+        extra["temp_bytes_touched"] = int(np.count_nonzero(w[:nbytes // 8] != -7) * 8)
+        extra["temp_guard_intact"] = bool(np.all(w[nbytes // 8:] == -7))
+        del wsg
     extra["launches_per_step"] = counts
     extra["kernel_time_per_step_ms"] = per_step
     del ws
