@@ -380,7 +380,9 @@ def single_product(ctx, name):
         elif name == "acc_4096_p65521_blocked":
             compare("table9_unblocked_3_levels", capi.WS_TWO_TEMP, 3)
             compare("blocked_t2_table2_2_levels", capi.WS_BLOCKED, 2, blocks=2)
-            compare("blocked_t3_table2_2_levels", capi.WS_BLOCKED, 2, blocks=3)
+            compare("blocked_t2_table2_1_level", capi.WS_BLOCKED, 1, blocks=2)
+            compare("blocked_t2_table9_1_level", capi.WS_BLOCKED_ACC, 1, blocks=2)
+            compare("blocked_t3_table2_1_level", capi.WS_BLOCKED, 1, blocks=3)
             compare("blocked_t4_table9_1_level", capi.WS_BLOCKED_ACC, 1, blocks=4)
         elif name == "t1_16384_p1048573":
             compare("classical_int8_digits", capi.WS_CLASSICAL, 0, capi.WS_BASE_I8_LIMBS)

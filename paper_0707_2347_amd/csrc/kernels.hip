@@ -501,9 +501,9 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_sk_kernel(GemmParams P) {
 }
 
 // Base products whose shape is whole TM x TM output tiles (TM = 32 or 64)
-// and 64-deep inner chunks with 16-byte aligned rows (every Winograd leaf of a
-// power-of-two product): one TM x TM output tile per workgroup over the full
-// inner dimension, split among the waves.  Wave w owns the SK-deep sub-chunks
+// and whole SK-deep inner sub-chunks with 16-byte aligned rows (every
+// Winograd leaf of a power-of-two product): one TM x TM output tile per
+// workgroup over the full inner dimension, split among the waves.  Wave w owns the SK-deep sub-chunks
 // w, w + WAVES, w + 2*WAVES, ... of the inner dimension; it streams their A
 // (TM x SK) and B (SK x TM) blocks into STAGES private LDS buffers by direct
 // global-to-LDS loads, waits on its own load counter and needs no workgroup
@@ -937,10 +937,15 @@ static bool tile_admissible(int kind, const GemmParams &P) {
     case TILE_BIG128:
         return WS_BIG_ENABLE && P.M % 128 == 0 && P.N % 128 == 0 && P.K % 16 == 0 && P.K > 0 &&
                dma_aligned(P);
+    // The split kernels deal whole sub-chunks of the inner dimension to their
+    // waves (some waves get one fewer): K only has to be a multiple of the
+    // sub-chunk depth.
     case TILE_DMA64:
-        return P.M % 64 == 0 && P.N % 64 == 0 && P.K % 64 == 0 && P.K > 0 && dma_aligned(P);
+        return P.M % 64 == 0 && P.N % 64 == 0 && P.K % WS_DMA64_SK == 0 && P.K > 0 &&
+               dma_aligned(P);
     case TILE_DMA32:
-        return P.M % 32 == 0 && P.N % 32 == 0 && P.K % 64 == 0 && P.K > 0 && dma_aligned(P);
+        return P.M % 32 == 0 && P.N % 32 == 0 && P.K % WS_DMA_SK == 0 && P.K > 0 &&
+               dma_aligned(P);
     case TILE_LDS128:
     case TILE_LDS64:
     case TILE_SK32:

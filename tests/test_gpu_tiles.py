@@ -20,9 +20,9 @@ def _admissible(kind, m, k, n):
     if kind == capi.WS_TILE_BIG128:
         return m % 128 == 0 and n % 128 == 0 and k % 16 == 0 and k > 0 and even
     if kind == capi.WS_TILE_DMA64:
-        return m % 64 == 0 and n % 64 == 0 and k % 64 == 0 and k > 0 and even
+        return m % 64 == 0 and n % 64 == 0 and k % 8 == 0 and k > 0 and even
     if kind == capi.WS_TILE_DMA32:
-        return m % 32 == 0 and n % 32 == 0 and k % 64 == 0 and k > 0 and even
+        return m % 32 == 0 and n % 32 == 0 and k % 16 == 0 and k > 0 and even
     return True
 
 
@@ -30,7 +30,15 @@ def _admissible(kind, m, k, n):
                                            ((384, 640, 256), 8388593, capi.WS_F64),
                                            ((256, 1024, 256), 16777213, capi.WS_I64),
                                            ((200, 300, 100), 16777213, capi.WS_F64),
-                                           ((128, 4096, 64), 8388593, capi.WS_F64)])
+                                           ((128, 4096, 64), 8388593, capi.WS_F64),
+                                           # inner dimensions that are not whole 64-deep
+                                           # chunks: the split kernels deal uneven
+                                           # numbers of sub-chunks to their waves
+                                           ((256, 48, 256), 65521, capi.WS_F64),
+                                           ((192, 336, 128), 8388593, capi.WS_F64),
+                                           ((128, 24, 64), 1048573, capi.WS_I64),
+                                           ((64, 16, 32), 16777213, capi.WS_F64),
+                                           ((320, 1040, 96), 8388593, capi.WS_F64)])
 def test_every_kind_is_exact(shape, p, dtype):
     m, k, n = shape
     A, B, C = inputs.uniform(71, m, k, n, p, with_c=True)
