@@ -476,3 +476,14 @@ def test_ipmm_acc_recurrence(shape, L):
     assert r.ops == G9(n, k, L)
     assert r.peak == 0
     assert r.ops >= replay_shape("ipmm", m, k, n, levels=L).ops
+
+
+@pytest.mark.parametrize("t", [1, 2, 3, 4])
+def test_blocked_makes_t_cubed_calls(t):
+    """Section 7.2: with C in four blocks the product takes 8 calls of the
+    base schedule; in general t^2 blocks of t calls each."""
+    n = 8 * t
+    r = replay_shape("blocked", n, n, n, levels=0, beta_nonzero=True, blocks=t)
+    assert r.calls["hl"] == t**3 and r.calls["blocked"] == 1
+    r = replay_shape("blocked_acc", n, n, n, levels=0, beta_nonzero=True, blocks=t)
+    assert r.calls["acc"] == t**3
