@@ -304,6 +304,27 @@ def test_empty_products(schedule, shape):
     assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, 3, beta, p))
 
 
+@pytest.mark.parametrize("schedule,shape,levels,beta,blocks", [
+    (capi.WS_BLOCKED, (512, 2048, 512), 1, 1, 2), (capi.WS_BLOCKED_ACC, (1024, 1024, 1024), 2, 1, 2),
+    (capi.WS_OVERWRITE, (512, 4096, 256), 1, 0, 0), (capi.WS_OVERWRITE, (256, 2048, 512), 1, 1, 0),
+    (capi.WS_IPMM_ACC, (512, 1024, 512), 1, 0, 0), (capi.WS_OVL, (1024, 1024, 1024), 2, 0, 0),
+    (capi.WS_TWO_TEMP, (1024, 1024, 1024), 3, 1, 0), (capi.WS_HL_THREE_TEMP, (512, 4096, 512), 2, 1, 0)])
+@pytest.mark.parametrize("p", [8388593, 16777213])
+def test_extreme_entries_under_schedules(schedule, shape, levels, beta, blocks, p):
+    """Every entry of A, B, C is p - 1 (the largest residue): since
+    (p-1)^2 = 1 mod p the product is k everywhere, so C = alpha*k + beta*(p-1)
+    mod p in closed form, whatever the schedule makes of the operands."""
+    m, k, n = shape
+    A = np.full((m, k), p - 1, dtype=np.int64)
+    B = np.full((k, n), p - 1, dtype=np.int64)
+    C = np.full((m, n), p - 1, dtype=np.int64)
+    alpha = p - 3
+    st, C2, _, _ = call(schedule, A, B, C, alpha, beta, p, levels, blocks=blocks)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    want = (alpha * k + beta * (p - 1)) % p
+    assert np.all(C2 == want)
+
+
 def test_attached_workspace_exact_size_and_no_hidden_allocation():
     t = __import__("torch")
     p = 65521
