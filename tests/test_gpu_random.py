@@ -70,7 +70,7 @@ def _case(rng):
         return sched, m, k, n, L, beta, t, p, name
 
 
-CASES = [_case(np.random.default_rng([77, i])) + (i,) for i in range(120)]
+CASES = [_case(np.random.default_rng([77, i])) + (i,) for i in range(300)]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "s%d_%dx%dx%d_l%d_b%d" % (
