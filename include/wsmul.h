@@ -189,7 +189,9 @@ WSMUL_API size_t wsmul_workspace_bytes(int64_t m, int64_t k, int64_t n, int dtyp
                              int levels, int beta_nonzero);
 
 /* Attach a caller-owned device workspace used when ws_args.workspace is NULL
- * (NULL/0 detaches).  The library never frees it. */
+ * (NULL/0 detaches).  The library never frees it.  Every such call uses the
+ * same memory: calls on different streams that use it must not overlap in
+ * time (order them, or pass each its own ws_args.workspace). */
 WSMUL_API int wsmul_set_workspace(void *ptr, size_t bytes);
 
 /* Default stream for calls whose ws_args.stream is NULL. */
