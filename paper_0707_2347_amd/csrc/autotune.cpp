@@ -195,6 +195,14 @@ bool search(const Key &key, Choice &best, Resolved *reject) {
             }
             admissible = true;
             reject->status = WS_OK;
+            // A plan of depth l runs at least 7^l base products (t^3 times
+            // that when blocked), each costed at no less than the 7 us
+            // launch floor: once that bound passes the best cost found, the
+            // candidate cannot win and its (large) plan is not built.
+            const double floor_us =
+                7.0 * std::pow(7.0, (double)r.levels) * (blocked ? (double)t * t * t : 1.0);
+            if (found && floor_us >= best.cost_us)
+                continue;
             PlanKey pk{};
             pk.m = key.m;
             pk.k = key.k;

@@ -42,6 +42,8 @@ struct KeyHash {
     }
 };
 std::unordered_map<PlanKey, std::shared_ptr<Plan>, KeyHash> g_plans;
+size_t g_plan_ops = 0;   // operations held by the cached plans (about 1 KB each)
+constexpr size_t PLAN_CACHE_PLANS = 512, PLAN_CACHE_OPS = size_t(1) << 20;
 
 int fail(int code, const std::string &msg) {
     g_err = msg;
@@ -82,9 +84,14 @@ std::shared_ptr<Plan> get_plan(const PlanKey &key) {
         return it->second;
     auto plan = std::make_shared<Plan>();
     build_plan(key, *plan);
-    if (g_plans.size() > 512)
+    // Bounded cache: start over when it would hold too many plans or
+    // operations (plans in use stay alive through their shared pointers).
+    if (g_plans.size() >= PLAN_CACHE_PLANS || g_plan_ops + plan->ops.size() > PLAN_CACHE_OPS) {
         g_plans.clear();
+        g_plan_ops = 0;
+    }
     g_plans.emplace(key, plan);
+    g_plan_ops += plan->ops.size();
     return plan;
 }
 
