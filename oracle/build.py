@@ -1,7 +1,8 @@
 """Build the oracle's C part (test infrastructure only).
 
 Compiles ``oracle/matmul_ref.c`` with gcc into ``oracle/liboracle.so``.  The
-checker is built here so tests can run; the product library never links it.
+reference product is built here so tests can run; the product library never
+links it.
 """
 import os
 import subprocess
