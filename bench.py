@@ -197,23 +197,31 @@ def cpu_baseline_rows(A, B, C, alpha, beta, p, budget_s=12.0):
     n = B.shape[1]
     Ai, Bi = A.astype(np.int64, copy=False), B.astype(np.int64, copy=False)
     Ci = None if C is None else C.astype(np.int64, copy=False)
-    rows = min(m, 16)
-    t_s = time.perf_counter()
-    ref.matmul_mod_p(Ai[:rows], Bi, None if Ci is None else Ci[:rows], alpha, beta, p,
-                     threads=threads)
-    dt = max(time.perf_counter() - t_s, 1e-4)
-    rows = int(min(m, max(16, rows * budget_s / dt)))
-    reps = 1 if rows < m else max(1, int(budget_s / max(dt * m / 16.0, 1e-3)))
-    log("cpu baseline: oracle on %d rows x %d x %d, %d threads, %d run(s)"
-        % (rows, k, n, threads, reps))
-    t_s = time.perf_counter()
-    for _ in range(reps):
-        ref.matmul_mod_p(Ai[:rows], Bi, None if Ci is None else Ci[:rows], alpha, beta, p,
+
+    def timed(r):
+        t_s = time.perf_counter()
+        ref.matmul_mod_p(Ai[:r], Bi, None if Ci is None else Ci[:r], alpha, beta, p,
                          threads=threads)
-    dt = (time.perf_counter() - t_s) / reps
+        return max(time.perf_counter() - t_s, 1e-4)
+
+    # Calibrate on a sample large enough to keep every thread busy (a few
+    # rows per thread undercount the rate), then fill the budget.
+    rows = min(m, 16)
+    dt = timed(rows)
+    while rows < m and dt < 0.5:
+        rows = min(m, rows * 4)
+        dt = timed(rows)
+    rows = m if dt / rows * m <= budget_s else int(max(16, budget_s * rows / dt))
+    log("cpu baseline: oracle on %d rows x %d x %d, %d threads" % (rows, k, n, threads))
+    # Repeat the sample while another run still fits the budget.
+    elapsed, reps = 0.0, 0
+    while reps == 0 or elapsed + elapsed / reps <= budget_s:
+        elapsed += timed(rows)
+        reps += 1
+    dt = elapsed / reps
     return {"value": round(2.0 * rows * k * n / dt / 1e9, 3), "unit": "Gop/s",
             "cores": threads, "kind": "oracle",
-            "sample": "rows 0..%d of the same product (%d x %d x %d), %d run(s) of %.1f s"
+            "sample": "rows 0..%d of the same product (%d x %d x %d), %d run(s) of %.3f s"
                       % (rows - 1, rows, k, n, reps, dt)}
 
 
