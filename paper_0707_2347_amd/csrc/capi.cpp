@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -27,7 +28,7 @@ thread_local ws_trace g_trace{};
 std::mutex g_mu;
 void *g_ws = nullptr;
 size_t g_ws_bytes = 0;
-hipStream_t g_stream = nullptr;
+std::atomic<hipStream_t> g_stream{nullptr};   // set and read from any thread
 
 struct KeyHash {
     size_t operator()(const PlanKey &k) const {
@@ -67,7 +68,7 @@ void set_stats(const ws_stats &s) {
     g_stats.peak_temp_bytes = peak;
 }
 
-hipStream_t default_stream() { return g_stream; }
+hipStream_t default_stream() { return g_stream.load(); }
 
 void set_batch_phases(uint64_t n) { g_stats.batch_phases = n; }
 
@@ -232,7 +233,7 @@ int execute(const ws_args &a, const PlanKey &key) {
     } catch (const std::exception &e) {
         return fail(WS_EINVAL, std::string("planner: ") + e.what());
     }
-    hipStream_t stream = a.stream ? static_cast<hipStream_t>(a.stream) : g_stream;
+    hipStream_t stream = a.stream ? static_cast<hipStream_t>(a.stream) : g_stream.load();
     const size_t ws_bytes = (size_t)plan->ws_elems * 8u;
     void *ws = nullptr;
     bool owned = false;
@@ -513,7 +514,7 @@ int wsmul_set_workspace(void *ptr, size_t bytes) {
 }
 
 int wsmul_set_stream(void *stream) {
-    g_stream = static_cast<hipStream_t>(stream);
+    g_stream.store(static_cast<hipStream_t>(stream));
     return WS_OK;
 }
 
