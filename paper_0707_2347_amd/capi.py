@@ -114,9 +114,6 @@ def lib():
             "wsmul_plan_export": (ctypes.c_int, [ctypes.POINTER(ws_args),
                                                  ctypes.POINTER(ws_op_desc), _i64,
                                                  ctypes.POINTER(_i64)]),
-        }
-        optional = {}
-        sig.update({
             "wsmul_batched": (ctypes.c_int, [ctypes.POINTER(ws_args), ctypes.c_int, _u32]),
             "wsmul_graph_capture": (ctypes.c_int, [ctypes.POINTER(ws_args), ctypes.c_int,
                                                    ctypes.POINTER(_vp)]),
@@ -130,14 +127,10 @@ def lib():
                                                 ctypes.POINTER(_dbl)]),
             "wsmul_set_tile": (ctypes.c_int, [_i64, _i64, _i64, _i64, ctypes.c_int, ctypes.c_int]),
             "wsmul_tune_plan": (ctypes.c_int, [ctypes.POINTER(ws_args), ctypes.c_int]),
-        })
+        }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
             f.restype, f.argtypes = res, args
-        for name, (res, args) in optional.items():
-            if hasattr(L, name):
-                f = getattr(L, name)
-                f.restype, f.argtypes = res, args
         _lib = L
     return _lib
 
