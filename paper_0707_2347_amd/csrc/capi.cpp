@@ -168,6 +168,34 @@ static void fill_stats(const Plan &plan, const ws_args &a, ws_stats &s) {
     s.base = a.base;
 }
 
+// One addition group.  The elementwise kernel indexes fewer than 2^31 items
+// per launch, so groups over blocks of 2^31 elements or more (quadrants of a
+// C of 2^33 entries, which fits the device when k is small) run as slices of
+// whole rows: the same group on fewer rows, one launch each.
+static hipError_t launch_add_rows(const OpDesc &op, const DevBufs &bufs, int dtype, int64_t p,
+                                  hipStream_t stream) {
+    const int64_t rows = op.out[0].rows, cols = op.out[0].cols;
+    const int64_t limit = (int64_t(1) << 31) - 1;
+    const int64_t per = std::max<int64_t>(1, limit / std::max<int64_t>(cols, 1));
+    if (rows <= per)
+        return launch_add(op, bufs, dtype, p, stream);
+    hipError_t err = hipSuccess;
+    for (int64_t r0 = 0; r0 < rows && err == hipSuccess; r0 += per) {
+        OpDesc s = op;
+        const int64_t nr = std::min(per, rows - r0);
+        for (int i = 0; i < s.nin; ++i) {
+            s.in[i].off += r0 * s.in[i].ld;
+            s.in[i].rows = nr;
+        }
+        for (int o = 0; o < s.nout; ++o) {
+            s.out[o].off += r0 * s.out[o].ld;
+            s.out[o].rows = nr;
+        }
+        err = launch_add(s, bufs, dtype, p, stream);
+    }
+    return err;
+}
+
 // Launch every operation of a plan on `stream`.
 int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, bool trace,
              void *scratch, size_t scratch_bytes) {
@@ -192,7 +220,7 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
             launch_timing() = LaunchTiming{ev[2 * i], ev[2 * i + 1], false};
         hipError_t err;
         if (op.kind == WS_OP_ADD)
-            err = launch_add(op, bufs, a.dtype, a.p, stream);
+            err = launch_add_rows(op, bufs, a.dtype, a.p, stream);
         else if (a.base == WS_BASE_I8_LIMBS)
             err = launch_gemm_limbs(op, bufs, a.dtype, a.p, stream);
         else
