@@ -276,7 +276,8 @@ enum {
     WS_TILE_LDS64 = 3,   /* 64 x 64, staged through registers (any shape)            */
     WS_TILE_DMA32 = 4,   /* 32 x 32, straight into LDS, inner dimension split by wave */
     WS_TILE_SK32 = 5,    /* 32 x 32, from global memory, inner dimension split (any)  */
-    WS_TILE_KINDS = 6
+    WS_TILE_DMA16 = 6,   /* 16 x 16, straight into LDS, inner dimension split by wave */
+    WS_TILE_KINDS = 7
 };
 WSMUL_API int wsmul_tune_tiles(int64_t m, int64_t k, int64_t n, int64_t p, int dtype, int reps,
                                int *best, double *times_us);

@@ -21,8 +21,8 @@ WS_F64, WS_I64 = 0, 1
 WS_BASE_AUTO, WS_BASE_F64_MFMA, WS_BASE_I8_LIMBS = 0, 1, 2
 WS_FLAG_CHECK, WS_FLAG_NOFUSE, WS_FLAG_TRACE, WS_FLAG_SYNC = 1, 2, 4, 8
 (WS_TILE_BIG128, WS_TILE_LDS128, WS_TILE_DMA64, WS_TILE_LDS64, WS_TILE_DMA32,
- WS_TILE_SK32) = range(6)
-WS_TILE_KINDS = 6
+ WS_TILE_SK32, WS_TILE_DMA16) = range(7)
+WS_TILE_KINDS = 7
 WS_MAX_IN, WS_MAX_OUT = 8, 6
 WS_BUF_A, WS_BUF_B, WS_BUF_C, WS_BUF_W = 0, 1, 2, 3
 WS_OP_ADD, WS_OP_GEMM = 0, 1

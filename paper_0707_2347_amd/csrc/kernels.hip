@@ -523,6 +523,12 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_sk_kernel(GemmParams P) {
 #ifndef WS_DMA_SK
 #define WS_DMA_SK 16
 #endif
+#ifndef WS_DMA16_WAVES
+#define WS_DMA16_WAVES 4
+#endif
+#ifndef WS_DMA16_STAGES
+#define WS_DMA16_STAGES 2
+#endif
 #ifndef WS_DMA64_WAVES
 #define WS_DMA64_WAVES 8
 #endif
@@ -575,8 +581,9 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
     constexpr int PROW = WAVES * TM * (TM + 2) * 8 <= LDS_BYTES ? TM + 2 : TM;
     constexpr int PSTRIDE = TM * PROW;
     constexpr int PW = WAVES * PSTRIDE * 8 <= LDS_BYTES ? WAVES : WAVES / 2;
-    static_assert(TM == 32 || TM == 64, "32 or 64");
+    static_assert(TM == 16 || TM == 32 || TM == 64, "16, 32 or 64");
     static_assert(SK == 8 || SK == 16, "sub-chunks of 8 or 16");
+    static_assert(TM != 16 || (SK == 16 && EPT >= 1), "16-wide tiles: 16-deep sub-chunks, <= 4 waves");
     static_assert(STAGES >= 2 && (STAGES - 2) * LPS <= 24, "load counter range");
     static_assert(PW * PSTRIDE * 8 <= LDS_BYTES, "partials fit the buffers");
     __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
@@ -614,7 +621,12 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
         }
 #pragma unroll
         for (int j = 0; j < BI; ++j) {
-            const int k = BROWS * j + lane / BPR, piece = (lane % BPR) ^ bswz<SK>(k);
+            // 16-wide tiles: B-rows of 128 bytes, so instead of a piece swizzle
+            // rows k and k ^ 1 trade places when bit 2 of k is set (an
+            // involution on the rows one instruction fills).
+            const int lr = BROWS * j + lane / BPR;
+            const int k = TM == 16 ? lr ^ ((lr >> 2) & 1) : lr;
+            const int piece = TM == 16 ? lane % BPR : (lane % BPR) ^ bswz<SK>(k);
             __builtin_amdgcn_global_load_lds(B + ((k0 + k) * P.ldb + n0) * 8 + piece * 16,
                                              base + A_BYTES + j * 1024, 16, 0, 0);
         }
@@ -662,8 +674,9 @@ __global__ __launch_bounds__(64 * WAVES) void gemm_dma_kernel(GemmParams P) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const int k = S * kq + s, col = 16 * j + li;
-                b[j][s] = cvt(*reinterpret_cast<const T *>(
-                    sb + k * (TM * 8) + ((col >> 1) ^ bswz<SK>(k)) * 16 + (col & 1) * 8));
+                const int off = TM == 16 ? (k ^ ((k >> 2) & 1)) * (TM * 8) + (col >> 1) * 16
+                                         : k * (TM * 8) + ((col >> 1) ^ bswz<SK>(k)) * 16;
+                b[j][s] = cvt(*reinterpret_cast<const T *>(sb + off + (col & 1) * 8));
             }
 #pragma unroll
         for (int s = 0; s < S; ++s)
@@ -946,6 +959,8 @@ static bool tile_admissible(int kind, const GemmParams &P) {
     case TILE_DMA32:
         return P.M % 32 == 0 && P.N % 32 == 0 && P.K % WS_DMA_SK == 0 && P.K > 0 &&
                dma_aligned(P);
+    case TILE_DMA16:
+        return P.M % 16 == 0 && P.N % 16 == 0 && P.K % 16 == 0 && P.K > 0 && dma_aligned(P);
     case TILE_LDS128:
     case TILE_LDS64:
     case TILE_SK32:
@@ -968,6 +983,12 @@ static int default_tile(const GemmParams &P) {
         return TILE_DMA64;
     if (mid >= 256)
         return TILE_LDS64;
+    // 32 x 32 tiles for at most three quarters of the CUs: 16 x 16 tiles
+    // spread the product over four times as many workgroups (measured faster
+    // up to 128 such tiles, slower at 225).
+    const int64_t small = ((P.M + 31) / 32) * ((P.N + 31) / 32);
+    if (small <= 192 && tile_admissible(TILE_DMA16, P))
+        return TILE_DMA16;
     if (tile_admissible(TILE_DMA32, P))
         return TILE_DMA32;
     return TILE_SK32;
@@ -1038,6 +1059,17 @@ static hipError_t launch_tile(int kind, GemmParams &P, bool vec2, hipStream_t s)
         const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(64 * W);
         if (c2) ws_launch((gemm_dma_kernel<T, true, 32, W, ST, SK>), grid, block, 0, s, P);
         else ws_launch((gemm_dma_kernel<T, false, 32, W, ST, SK>), grid, block, 0, s, P);
+        break;
+    }
+    case TILE_DMA16: {
+        constexpr int W = WS_DMA16_WAVES, ST = WS_DMA16_STAGES, SK = 16;
+        const bool c2 = dma_centre((int64_t)P.p, P.K, 16, W, SK);
+        P.kc_tiles = fold_chunks((int64_t)P.p, c2, P.K, W, SK);
+        P.tiles_m = (int32_t)(P.M / 16);
+        P.tiles_n = (int32_t)(P.N / 16);
+        const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(64 * W);
+        if (c2) ws_launch((gemm_dma_kernel<T, true, 16, W, ST, SK>), grid, block, 0, s, P);
+        else ws_launch((gemm_dma_kernel<T, false, 16, W, ST, SK>), grid, block, 0, s, P);
         break;
     }
     default: {

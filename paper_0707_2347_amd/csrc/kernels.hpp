@@ -46,10 +46,11 @@ hipError_t launch_add(const ws_op_desc &op, const DevBufs &bufs, int dtype, int6
 // header): 128 x 128 tiles pipelined through LDS by direct loads, or staged
 // through registers; 64 x 64 tiles by direct loads with split inner
 // dimension, or register-staged; 32 x 32 tiles by direct loads with split
-// inner dimension, or straight from global memory.
+// inner dimension, or straight from global memory; 16 x 16 tiles by direct
+// loads with split inner dimension.
 enum : int {
     TILE_BIG128 = 0, TILE_LDS128 = 1, TILE_DMA64 = 2, TILE_LDS64 = 3, TILE_DMA32 = 4,
-    TILE_SK32 = 5, TILE_KINDS = 6
+    TILE_SK32 = 5, TILE_DMA16 = 6, TILE_KINDS = 7
 };
 // Kind chosen for products of this shape and modulus (measured or pinned),
 // or -1 for the default rule.  choose_tile with kind -1 forgets the choice.

@@ -23,6 +23,8 @@ def _admissible(kind, m, k, n):
         return m % 64 == 0 and n % 64 == 0 and k % 8 == 0 and k > 0 and even
     if kind == capi.WS_TILE_DMA32:
         return m % 32 == 0 and n % 32 == 0 and k % 16 == 0 and k > 0 and even
+    if kind == capi.WS_TILE_DMA16:
+        return m % 16 == 0 and n % 16 == 0 and k % 16 == 0 and k > 0 and even
     return True
 
 
