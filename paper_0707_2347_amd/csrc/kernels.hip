@@ -167,8 +167,11 @@ hipError_t launch_add(const ws_op_desc &op, const DevBufs &bufs, int dtype, int6
 // grid, each wave (BM/2) x (BN/2) of 16 x 16 matrix-core tiles, K-tiles of 16
 // double-buffered through LDS.  In the matrix-core step s of a K-tile, lane l
 // supplies k = 4*(l/16) + s, so each lane's four A values are contiguous in
-// LDS; B uses the same k assignment.
-template <typename T, int BM, int BN, bool CENTRE, bool VEC2>
+// LDS; B uses the same k assignment.  PF register stages: with PF = 2 the
+// loads of K-tile t+2 are issued while t is multiplied and t+1 waits in the
+// other stage, so every load has a whole K-tile of cover (worth it only where
+// the extra registers do not cost occupancy).
+template <typename T, int BM, int BN, bool CENTRE, bool VEC2, int PF = 1>
 __device__ __forceinline__ void gemm_lds_tile(const GemmParams &P, int32_t tm, int32_t tn,
                                               double (*As)[BM * (16 + 2)], double (*Bs)[16 * BN]) {
     constexpr int BK = 16, APAD = 2;
@@ -186,9 +189,10 @@ __device__ __forceinline__ void gemm_lds_tile(const GemmParams &P, int32_t tm, i
     // elements per access.
     constexpr int A_PAIRS = BM * BK / 2 / 256;   // per thread
     constexpr int B_PAIRS = BK * BN / 2 / 256;
-    double ra[A_PAIRS][2], rb[B_PAIRS][2];
+    static_assert(PF == 1 || PF == 2, "one or two register stages");
+    double ra[A_PAIRS][2], rb[B_PAIRS][2], ra2[A_PAIRS][2], rb2[B_PAIRS][2];
 
-    auto gload = [&](int64_t k0) {
+    auto gload = [&](int64_t k0, double (&ra)[A_PAIRS][2], double (&rb)[B_PAIRS][2]) {
 #pragma unroll
         for (int j = 0; j < A_PAIRS; ++j) {
             const int v = tid + 256 * j, row = v / (BK / 2), cp = v % (BK / 2);
@@ -230,7 +234,7 @@ __device__ __forceinline__ void gemm_lds_tile(const GemmParams &P, int32_t tm, i
             rb[j][1] = (CENTRE && x1 > P.half) ? x1 - P.p : x1;
         }
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](int buf, const double (&ra)[A_PAIRS][2], const double (&rb)[B_PAIRS][2]) {
 #pragma unroll
         for (int j = 0; j < A_PAIRS; ++j) {
             const int v = tid + 256 * j, row = v / (BK / 2), cp = v % (BK / 2);
@@ -262,15 +266,19 @@ __device__ __forceinline__ void gemm_lds_tile(const GemmParams &P, int32_t tm, i
 
     const int64_t ktiles = (P.K + BK - 1) / BK;
     if (ktiles > 0) {
-        gload(0);
-        sstore(0);
+        gload(0, ra, rb);
+        sstore(0, ra, rb);
     }
+    if (PF == 2 && ktiles > 1)
+        gload(BK, ra2, rb2);
     __syncthreads();
     int since_fold = 0;
-    for (int64_t t = 0; t < ktiles; ++t) {
-        const int cur = (int)(t & 1);
-        if (t + 1 < ktiles)
-            gload((t + 1) * BK);
+    // K-tile t from LDS buffer cur: first request K-tile t+PF into (la, lb),
+    // multiply, then move K-tile t+1 from (sa, sb) into the other buffer.
+    auto step = [&](int64_t t, int cur, double (&la)[A_PAIRS][2], double (&lb)[B_PAIRS][2],
+                    const double (&sa)[A_PAIRS][2], const double (&sb)[B_PAIRS][2]) {
+        if (t + PF < ktiles)
+            gload((t + PF) * BK, la, lb);
         double af[FM][4];
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
@@ -295,11 +303,21 @@ __device__ __forceinline__ void gemm_lds_tile(const GemmParams &P, int32_t tm, i
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i][s], bf[j], acc[i][j], 0, 0, 0);
         }
         if (t + 1 < ktiles)
-            sstore(cur ^ 1);
+            sstore(cur ^ 1, sa, sb);
         __syncthreads();
         if (P.kc_tiles > 0 && ++since_fold == P.kc_tiles) {
             fold();
             since_fold = 0;
+        }
+    };
+    if (PF == 1) {
+        for (int64_t t = 0; t < ktiles; ++t)
+            step(t, (int)(t & 1), ra, rb, ra, rb);
+    } else {
+        for (int64_t t = 0; t < ktiles; t += 2) {
+            step(t, 0, ra, rb, ra2, rb2);
+            if (t + 1 < ktiles)
+                step(t + 1, 1, ra2, rb2, ra, rb);
         }
     }
 
@@ -1330,8 +1348,9 @@ __device__ void batch_add_chunk(const GemmParams &P, int64_t chunk) {
 
 // Base products run as 64 x 64 tiles here: with many products in flight the
 // launch is throughput-bound, and the smaller tile keeps register use low
-// enough for several workgroups per CU.
-__global__ __launch_bounds__(256) void batch_kernel(const BatchOp *ops, const int2 *tasks,
+// enough for several workgroups per CU.  Two register stages of operand
+// loads, held to three waves per SIMD (three workgroups per CU).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void batch_kernel(const BatchOp *ops, const int2 *tasks,
                                                     int64_t ntasks) {
     __shared__ LdsTile<64, 64> sh;
     // Records and tasks do not change during the launch: read them through
@@ -1347,11 +1366,11 @@ __global__ __launch_bounds__(256) void batch_kernel(const BatchOp *ops, const in
         if (op.kind == WS_OP_GEMM) {
             const int32_t tm = t.y / op.g.tiles_n, tn = t.y % op.g.tiles_n;
             if (op.centre) {
-                if (op.vec2) gemm_lds_tile<double, 64, 64, true, true>(op.g, tm, tn, sh.As, sh.Bs);
-                else gemm_lds_tile<double, 64, 64, true, false>(op.g, tm, tn, sh.As, sh.Bs);
+                if (op.vec2) gemm_lds_tile<double, 64, 64, true, true, 2>(op.g, tm, tn, sh.As, sh.Bs);
+                else gemm_lds_tile<double, 64, 64, true, false, 2>(op.g, tm, tn, sh.As, sh.Bs);
             } else {
-                if (op.vec2) gemm_lds_tile<double, 64, 64, false, true>(op.g, tm, tn, sh.As, sh.Bs);
-                else gemm_lds_tile<double, 64, 64, false, false>(op.g, tm, tn, sh.As, sh.Bs);
+                if (op.vec2) gemm_lds_tile<double, 64, 64, false, true, 2>(op.g, tm, tn, sh.As, sh.Bs);
+                else gemm_lds_tile<double, 64, 64, false, false, 2>(op.g, tm, tn, sh.As, sh.Bs);
             }
         } else {
             batch_add_chunk(op.g, t.y);
