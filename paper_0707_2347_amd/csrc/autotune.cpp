@@ -41,7 +41,7 @@ double gemm_f64_us(int64_t M, int64_t N, int64_t K, int64_t p) {
     if (big >= 256 && M % 128 == 0 && N % 128 == 0 && K % 16 == 0)
         rate = folds ? 57e12 : 60e12;             // pipelined 128 x 128 tiles
     else if (big >= 512)
-        rate = folds ? 50e12 : 58e12;             // LDS-staged 128 x 128 tiles, centred when folding
+        rate = folds ? 50e12 : 58e12;             // large products of other shapes, register-staged
     else if (mid >= 256)
         rate = (M % 64 == 0 && N % 64 == 0 && K % 64 == 0) ? 45e12 : 30e12;
     else
