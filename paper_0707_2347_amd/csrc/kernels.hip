@@ -993,9 +993,15 @@ static int default_tile(const GemmParams &P) {
         return TILE_SK32;   // C <- beta*C only
     const int64_t big = ((P.M + 127) / 128) * ((P.N + 127) / 128);
     const int64_t mid = ((P.M + 63) / 64) * ((P.N + 63) / 64);
-    if (big >= 256 && tile_admissible(TILE_BIG128, P))
+    // Whole 128 x 128 tiles: the pipelined kernel, unless its last round of
+    // workgroups (one per CU) would be so partial that the 64 x 64 direct
+    // kernel (also one per CU, four times the workgroups) finishes first; a
+    // 64 x 64 round measured 0.26 of a 128 x 128 one.
+    // (Every shape the pipelined kernel takes, the direct one takes too.)
+    if (tile_admissible(TILE_BIG128, P) && mid >= 256 &&
+        std::ceil((double)big / 256.0) <= 0.26 * std::ceil((double)mid / 256.0))
         return TILE_BIG128;
-    if (big >= 512) {
+    if (big >= 512 && !tile_admissible(TILE_DMA64, P)) {
         // Register-staged tiles for large products of other shapes: 128 x 128
         // tiles (two workgroups per CU) cover an area about 4% faster than
         // 64 x 64 tiles (four per CU), but a partial last round of workgroups
