@@ -1012,14 +1012,20 @@ static int default_tile(const GemmParams &P) {
         if (r128 <= r64)
             return TILE_LDS128;
     }
-    if (mid >= 256 && tile_admissible(TILE_DMA64, P))
+    const int64_t small = ((P.M + 31) / 32) * ((P.N + 31) / 32);
+    // Direct 64 x 64 or 32 x 32 tiles (one workgroup per CU either way): the
+    // same round count, a 32 x 32 round measured 0.29 of a 64 x 64 one.
+    if (mid >= 256 && tile_admissible(TILE_DMA64, P)) {
+        if (tile_admissible(TILE_DMA32, P) &&
+            std::ceil((double)mid / 256.0) > 0.29 * std::ceil((double)small / 256.0))
+            return TILE_DMA32;
         return TILE_DMA64;
+    }
     if (mid >= 256)
         return TILE_LDS64;
     // 32 x 32 tiles for at most three quarters of the CUs: 16 x 16 tiles
     // spread the product over four times as many workgroups (measured faster
     // up to 128 such tiles, slower at 225).
-    const int64_t small = ((P.M + 31) / 32) * ((P.N + 31) / 32);
     if (small <= 192 && tile_admissible(TILE_DMA16, P))
         return TILE_DMA16;
     if (tile_admissible(TILE_DMA32, P))
