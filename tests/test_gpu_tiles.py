@@ -109,3 +109,20 @@ def test_tile_argument_errors():
     assert capi.wsmul_tune_tiles(0, 5, 5, 65521)[0] == capi.WS_EINVAL
     assert capi.wsmul_tune_tiles(5, 5, 5, 1)[0] == capi.WS_EMODULUS
     assert capi.wsmul_set_tile(5, 5, 5, 65521, capi.WS_F64, capi.WS_TILE_KINDS) == capi.WS_EINVAL
+
+
+@pytest.mark.parametrize("shape,p", [((1536, 64, 1536), 65521),        # 32 x 32 direct by rounds
+                                     ((2304, 64, 2304), 8388593),      # 64 x 64 direct by rounds
+                                     ((3072, 48, 3072), 65521),        # 64 x 64 direct by rounds
+                                     ((3000, 40, 3000), 1048573),      # 64 x 64 register-staged
+                                     ((4000, 32, 4000), 65521),        # 128 x 128 register-staged
+                                     ((768, 96, 768), 16777213)])      # 32 x 32 direct
+def test_default_rule_shapes_are_exact(shape, p):
+    """Products that the round-count rules send to each kind, on the default
+    choice, against the oracle."""
+    m, k, n = shape
+    A, B, C = inputs.uniform(75, m, k, n, p, with_c=True)
+    print("default rule", shape, p, flush=True)
+    st, C2, _, _ = call(capi.WS_CLASSICAL, A, B, C, 2, 3, p, 0)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, 2, 3, p))
