@@ -1013,23 +1013,33 @@ static int default_tile(const GemmParams &P) {
             return TILE_LDS128;
     }
     const int64_t small = ((P.M + 31) / 32) * ((P.N + 31) / 32);
+    const int64_t tiny = ((P.M + 15) / 16) * ((P.N + 15) / 16);
+    // Direct 32 x 32 tiles, or 16 x 16 ones: for at most three quarters of
+    // the CUs' worth of 32 x 32 tiles the 16 x 16 kernel spreads the product
+    // over four times as many workgroups (measured faster up to 128 such
+    // tiles, slower at 225); beyond that compare rounds (five 16 x 16
+    // workgroups per CU, a round measured 1.1 to 1.36 of a 32 x 32 one).
+    auto direct32 = [&]() {
+        if (tile_admissible(TILE_DMA16, P) &&
+            (small <= 192 ||
+             1.25 * std::ceil((double)tiny / 1280.0) <= std::ceil((double)small / 256.0)))
+            return (int)TILE_DMA16;
+        return (int)TILE_DMA32;
+    };
     // Direct 64 x 64 or 32 x 32 tiles (one workgroup per CU either way): the
     // same round count, a 32 x 32 round measured 0.29 of a 64 x 64 one.
     if (mid >= 256 && tile_admissible(TILE_DMA64, P)) {
         if (tile_admissible(TILE_DMA32, P) &&
             std::ceil((double)mid / 256.0) > 0.29 * std::ceil((double)small / 256.0))
-            return TILE_DMA32;
+            return direct32();
         return TILE_DMA64;
     }
     if (mid >= 256)
         return TILE_LDS64;
-    // 32 x 32 tiles for at most three quarters of the CUs: 16 x 16 tiles
-    // spread the product over four times as many workgroups (measured faster
-    // up to 128 such tiles, slower at 225).
+    if (tile_admissible(TILE_DMA32, P))
+        return direct32();
     if (small <= 192 && tile_admissible(TILE_DMA16, P))
         return TILE_DMA16;
-    if (tile_admissible(TILE_DMA32, P))
-        return TILE_DMA32;
     return TILE_SK32;
 }
 
