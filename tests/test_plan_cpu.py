@@ -40,6 +40,22 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
+def test_binding_constants_match_the_header():
+    """Every enumerator and size #define of include/wsmul.h has the same
+    value in the binding (a kind or schedule added on one side only fails)."""
+    header = open(os.path.join(ROOT, "include", "wsmul.h")).read()
+    header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    values = {}
+    for name, expr in re.findall(r"\b(WS_[A-Z0-9_]+)\s*=\s*([^,}\n]+)", header):
+        expr = expr.strip().replace("1u", "1")
+        values[name] = eval(expr, {"__builtins__": {}})
+    for name, val in re.findall(r"#define\s+(WS_MAX_\w+)\s+(\d+)", header):
+        values[name] = int(val)
+    assert len(values) >= 40
+    for name, val in values.items():
+        assert getattr(capi, name) == val, name
+
+
 def _interp(schedule, m, k, n, p, alpha, beta, levels, seed, fuse=True, dtype=capi.WS_F64,
             blocks=0):
     A, B, C = inputs.uniform(seed, m, k, n, p, with_c=True)
