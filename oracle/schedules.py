@@ -25,9 +25,9 @@ A "garbage" mode fills freshly allocated temporaries, and the operands an
 overwriting callee is allowed to destroy, with random residues.  A schedule
 that reads a dead value then returns a wrong product, which the tests catch.
 
-Parity unpinned: the final contents of the inputs that an overwriting
-schedule destroys (Tables 3-8, Algorithm 1) are pinned independently only
-after one level; beyond that they rest on this replay alone.
+The final contents of inputs an overwriting schedule destroys (Tables 3-8,
+Algorithm 1) are pinned at every depth by closed-form recursions written from
+Section 2's block definitions, independently of this replay.
 
 Notation (Section 2): A is m x k, B is k x n, C is m x n, each split into
 quadrants X11, X12, X21, X22 of half the rows and half the columns.
