@@ -27,7 +27,11 @@
  *   argument checks run before any launch, so WS_EINVAL, WS_ESHAPE,
  *   WS_EMODULUS and WS_ESCHEDULE leave A, B and C untouched.  After WS_EHIP
  *   the contents of C (and of A, B for overwriting schedules) are
- *   unspecified.  wsmul_last_error() returns a thread-local message.
+ *   unspecified, and memory the call allocated is released (stream-ordered)
+ *   all the same.  wsmul_last_error() returns a thread-local message.  For
+ *   tests of that path, the environment variable WSMUL_FAULT_AT=i makes a
+ *   single-product call stop before launching its operation i and return
+ *   WS_EHIP (nothing is launched when i = 0).
  * - Read-only schedules leave A and B bitwise unchanged.  WS_OVERWRITE (and
  *   the sub-schedules that overwrite) leave A and/or B in a state that is a
  *   fixed function of the inputs and the schedule's tables.
@@ -158,6 +162,10 @@ typedef struct ws_stats {
     uint64_t scratch_bytes;        /* INT8 base: digit planes of the largest base product
                                       (kernel scratch, not a schedule temporary)       */
     uint64_t batch_phases;         /* batches: persistent launches (phases) issued     */
+    uint64_t live_alloc_bytes;     /* device bytes still held by single-product calls of
+                                      this process after the call returned (owned
+                                      workspace and digit scratch not yet released);
+                                      0 once every call has cleaned up, errors included */
 } ws_stats;
 
 /*
@@ -216,7 +224,9 @@ WSMUL_API const char *wsmul_version(void);
 
 /* ------------------------------------------------------------------------
  * Batches.  Many independent products (binary64 storage and base), each with
- * its own shape, modulus and schedule (WS_AUTO and levels = -1 allowed).
+ * its own shape, modulus and schedule (WS_AUTO and levels = -1 allowed).  A
+ * product left at WS_BASE_AUTO runs on the binary64 base (the autotuner then
+ * prices only that base); WS_BASE_I8_LIMBS or int64 storage is WS_EINVAL.
  * Operation j of every product forms phase j; the operations of a phase are
  * independent, so each phase is ONE persistent launch whose workgroups walk
  * its tasks -- one 64 x 64 output tile of a base product or one chunk of an

@@ -53,7 +53,7 @@ class ws_stats(ctypes.Structure):
                 ("gemm_launches", _u64), ("element_additions", _u64),
                 ("base_flops", _u64), ("rows", _u64), ("levels", _u64),
                 ("schedule", _i64), ("base", _i64), ("scratch_bytes", _u64),
-                ("batch_phases", _u64)]
+                ("batch_phases", _u64), ("live_alloc_bytes", _u64)]
 
 
 class ws_trace(ctypes.Structure):

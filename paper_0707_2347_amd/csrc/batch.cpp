@@ -51,7 +51,13 @@ int plan_batch(const ws_args *probs, int count, Batch &b) {
     for (int i = 0; i < count; ++i) {
         PlanKey key;
         Resolved res;
-        const int rc = prepare(&probs[i], b.norm[i], key, res);
+        // The batch kernel runs the binary64 base only: a product that leaves
+        // the base to the library gets that base before the autotuner prices
+        // its schedule and depth.
+        ws_args req = probs[i];
+        if (req.base == WS_BASE_AUTO)
+            req.base = WS_BASE_F64_MFMA;
+        const int rc = prepare(&req, b.norm[i], key, res);
         if (rc != WS_OK)
             return rc;
         if (b.norm[i].dtype != WS_F64 || b.norm[i].base == WS_BASE_I8_LIMBS)

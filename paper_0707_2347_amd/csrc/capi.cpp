@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -29,6 +30,9 @@ std::mutex g_mu;
 void *g_ws = nullptr;
 size_t g_ws_bytes = 0;
 std::atomic<hipStream_t> g_stream{nullptr};   // set and read from any thread
+// Device bytes the single-product calls hold at the moment (workspace and
+// digit scratch they allocated and have not yet released, stream-ordered).
+std::atomic<uint64_t> g_live_bytes{0};
 
 struct KeyHash {
     size_t operator()(const PlanKey &k) const {
@@ -213,9 +217,20 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
                 return fail(WS_EHIP, "hipEventCreate failed");
             }
     }
+    // Host-side failure injection for tests of the error path: with
+    // WSMUL_FAULT_AT=i the call stops before launching operation i and
+    // reports WS_EHIP, as if that launch had failed.
+    long fault_at = -1;
+    if (const char *f = std::getenv("WSMUL_FAULT_AT"))
+        fault_at = std::strtol(f, nullptr, 10);
     int rc = WS_OK;
     for (size_t i = 0; i < plan.ops.size() && rc == WS_OK; ++i) {
         const OpDesc &op = plan.ops[i];
+        if (fault_at >= 0 && (size_t)fault_at == i) {
+            rc = fail(WS_EHIP, "injected failure before operation " + std::to_string(i) +
+                                   " (WSMUL_FAULT_AT)");
+            break;
+        }
         if (trace)
             launch_timing() = LaunchTiming{ev[2 * i], ev[2 * i + 1], false};
         hipError_t err;
@@ -279,13 +294,20 @@ int execute(const ws_args &a, const PlanKey &key) {
             if (hipMallocAsync(&ws, ws_bytes, stream) != hipSuccess)
                 return fail(WS_ENOMEM, "workspace allocation failed");
             owned = true;
+            g_live_bytes += ws_bytes;
         }
     }
+    auto release_ws = [&]() {
+        if (owned) {
+            (void)hipFreeAsync(ws, stream);
+            g_live_bytes -= ws_bytes;
+        }
+    };
     if (a.flags & WS_FLAG_CHECK) {
         const int rc = check_ranges(a, stream);
         if (rc != WS_OK) {
-            if (owned)
-                (void)hipFreeAsync(ws, stream);
+            release_ws();
+            g_stats.live_alloc_bytes = g_live_bytes.load();
             return rc;
         }
     }
@@ -298,18 +320,22 @@ int execute(const ws_args &a, const PlanKey &key) {
                 scratch_bytes = std::max(scratch_bytes,
                                          digit_scratch_bytes(op.a.rows, op.b.cols, op.a.cols));
         if (scratch_bytes && hipMallocAsync(&scratch, scratch_bytes, stream) != hipSuccess) {
-            if (owned)
-                (void)hipFreeAsync(ws, stream);
+            release_ws();
+            g_stats.live_alloc_bytes = g_live_bytes.load();
             return fail(WS_ENOMEM, "digit scratch allocation failed");
         }
+        if (scratch)
+            g_live_bytes += scratch_bytes;
     }
     const int rc = run_plan(*plan, a, ws, stream, (a.flags & WS_FLAG_TRACE) != 0, scratch,
                             scratch_bytes);
-    if (scratch)
+    if (scratch) {
         (void)hipFreeAsync(scratch, stream);
-    if (owned)
-        (void)hipFreeAsync(ws, stream);
+        g_live_bytes -= scratch_bytes;
+    }
+    release_ws();
     fill_stats(*plan, a, g_stats);
+    g_stats.live_alloc_bytes = g_live_bytes.load();
     g_stats.internal_alloc_bytes = (owned ? ws_bytes : 0) + scratch_bytes;
     g_stats.scratch_bytes = scratch_bytes;
     if (g_stats.workspace_bytes > g_stats.peak_temp_bytes)

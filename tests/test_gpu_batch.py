@@ -1,9 +1,7 @@
 """GPU parity of the batched persistent launch and its hipGraph replay.
 
-Each product of a batch is checked against the oracle: small batches in full,
-the 2000-product workload (sizes log-uniform in [64, 2048], three moduli) on
-sampled entries computed one by one, in the launch configuration the
-benchmark times (one graph replay)."""
+Each product of a batch is checked in full against the oracle (the
+2000-product workload in test_gpu_configs.py)."""
 import numpy as np
 import pytest
 
@@ -111,39 +109,6 @@ def test_graph_replays_with_eager_work_between():
         capi.wsmul_graph_destroy(handle)
 
 
-def test_batch_workload_2000_sampled():
-    """All 2000 products of the batch workload in one graph replay; 6 sampled
-    entries per product, each computed by the oracle when its inputs are made."""
-    t = _torch()
-    probs = inputs.batch_problems()
-    assert len(probs) == 2000
-    rng = np.random.default_rng(11)
-    args, dev, want = [], [], []
-    for pr in probs:
-        A, B = inputs.batch_inputs(pr)
-        m, k, n, p = pr["m"], pr["k"], pr["n"], pr["p"]
-        rows = rng.integers(0, m, size=6)
-        cols = rng.integers(0, n, size=6)
-        want.append((rows, cols, ref.matmul_entries(A, B, None, 1, 0, p, rows, cols)))
-        dA = t.from_numpy(A).cuda()
-        dB = t.from_numpy(B).cuda()
-        dC = t.full((m, n), -1.0, dtype=t.float64, device="cuda:0")
-        dev.append((dA, dB, dC))
-        args.append(capi.make_args(m, k, n, p, dA, dB, dC, 1, 0, capi.WS_AUTO, -1,
-                                   base=capi.WS_BASE_F64_MFMA, stream=t.cuda.current_stream()))
-    st, handle = capi.wsmul_graph_capture(args)
-    assert st == capi.WS_OK, capi.wsmul_last_error()
-    try:
-        assert capi.wsmul_graph_launch(handle, t.cuda.current_stream()) == capi.WS_OK
-        assert capi.wsmul_graph_check(handle, t.cuda.current_stream()) == capi.WS_OK
-        t.cuda.synchronize()
-        for (rows, cols, w), (dA, dB, dC) in zip(want, dev):
-            got = dC[t.from_numpy(rows).cuda(), t.from_numpy(cols).cuda()].cpu().numpy()
-            assert np.array_equal(got.astype(np.int64), w)
-    finally:
-        capi.wsmul_graph_destroy(handle)
-
-
 @pytest.mark.parametrize("shape,p,beta", [((300, 200, 100), 65521, 0), ((1024, 1024, 1024), 1048573, 0),
                                           ((512, 512, 512), 8388593, 3)])
 def test_autotuned_calls(shape, p, beta):
@@ -153,3 +118,22 @@ def test_autotuned_calls(shape, p, beta):
     st, C2, _, _ = call(capi.WS_AUTO, A, B, C, 5, beta, p, -1, base=capi.WS_BASE_AUTO)
     assert st == capi.WS_OK, capi.wsmul_last_error()
     assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, 5, beta, p))
+
+
+def test_batch_with_base_left_to_the_library():
+    """Products whose base is left at WS_BASE_AUTO (the zero default) run on
+    the binary64 base inside a batch, even at sizes where the autotuner would
+    pick the 8-bit digit base for a single call."""
+    t = _torch()
+    specs = [(2048, 2048, 2048, 65521, capi.WS_AUTO, -1, 0), (1024, 1024, 1024, 1048573, capi.WS_AUTO, -1, 4),
+             (300, 500, 200, 8388593, capi.WS_TWO_TEMP, 1, 0)]
+    host, dev, args = _mk_batch(specs, 6)
+    for a in args:
+        a.base = capi.WS_BASE_AUTO
+    st = capi.wsmul_batched(args, capi.WS_FLAG_SYNC)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    t.cuda.synchronize()
+    for (A, B, C, alpha, beta, p), (dA, dB, dC) in zip(host, dev):
+        got = dC.cpu().numpy().astype(np.int64)
+        assert np.array_equal(got, ref.matmul_mod_p(A, B, C, alpha, beta, p))
+

@@ -5,8 +5,9 @@ under Table 1 at one level: the post-additions work on C's quadrants of about
 46341 x 46341 = 2^31 entries (odd and even row lengths, so both the 8-byte
 and the 16-byte access paths), C itself is 69 GB.  Unfused, the
 post-additions are addition groups over the quadrants; fused, they are the
-epilogues of the quadrant products.  Entries sampled at random and on every
-slice boundary are compared with the oracle."""
+epilogues of the quadrant products.  Entries sampled at random, and every
+entry of the rows on both sides of each slice boundary, are compared with the
+oracle."""
 import numpy as np
 import pytest
 
@@ -42,6 +43,11 @@ def test_quadrants_of_two_to_the_31_entries(m):
                            np.tile([0, h - 1, h, n - 1], 2 * len(edge))])
     want = ref.matmul_entries(A, B, None, 1, 0, p, rows, cols)
     ri, ci = torch.from_numpy(rows).to("cuda:0"), torch.from_numpy(cols).to("cuda:0")
+    # Whole rows on both sides of every slice boundary, in both row halves.
+    full_rows = np.array(sorted({r + q for r in edge + [per - 2, per + 1] for q in (0, h)
+                                 if 0 <= r + q < m}), dtype=np.int64)
+    want_rows = ref.matmul_mod_p(A[full_rows], B, None, 1, 0, p)
+    fr = torch.from_numpy(full_rows).to("cuda:0")
     try:
         for flags in (capi.WS_FLAG_NOFUSE, 0):
             print("m = n =", m, "flags", flags, flush=True)
@@ -53,6 +59,8 @@ def test_quadrants_of_two_to_the_31_entries(m):
             assert st == capi.WS_OK, capi.wsmul_last_error()
             got = dC[ri, ci].cpu().numpy().astype(np.int64)
             assert np.array_equal(got, want), flags
+            got_rows = dC[fr].cpu().numpy().astype(np.int64)
+            assert np.array_equal(got_rows, want_rows), flags
     finally:
         del dC, dA, dB
         torch.cuda.empty_cache()

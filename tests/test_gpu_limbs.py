@@ -28,10 +28,14 @@ def test_digit_base_classical(shape, dtype, p):
         assert np.array_equal(C2, ref.matmul_mod_p(A, B, C, alpha, beta, p)), (alpha, beta)
 
 
+@pytest.mark.parametrize("shape", [(64, 4096, 48), (32, 16384, 32), (32, 32768, 32)])
 @pytest.mark.parametrize("p", [65521, 1048573, 8388593, 16711421])
-def test_digit_extremes(p):
-    """Residues whose centred value has the largest digits, long K."""
-    m, k, n = 64, 4096, 48
+def test_digit_extremes(p, shape):
+    """Residues whose centred value has the largest digits, up to the longest
+    inner dimension the digit base accepts (32768, where a weight class of
+    three digit products comes within a factor 1.33 of the int32 range)."""
+    m, k, n = shape
+    print("digit extremes", shape, p, flush=True)
     h = (p - 1) // 2
     rng = np.random.default_rng(p)
     choices = np.array([h, h + 1, p - 1, 1, 0], dtype=np.int64)
