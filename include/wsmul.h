@@ -186,6 +186,29 @@ WSMUL_API int wsmul_mod_p_i64(int64_t m, int64_t k, int64_t n, int64_t p,
 /* Everything explicit (leading dimensions, dtype, base, stream, workspace). */
 WSMUL_API int wsmul_mod_p_ex(const ws_args *args);
 
+/* Size of the static device scratch of wsmul_mod_p_noalloc, per GPU. */
+#define WSMUL_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/*
+ * wsmul_mod_p_ex for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same product, plan and kernels, with the schedule's temporaries and the
+ * 8-bit digit planes taken from one static device array of
+ * WSMUL_NOALLOC_SCRATCH_BYTES bytes per GPU instead of an allocation: no
+ * hipMalloc, hipFree or other allocating call, no synchronisation.  The first
+ * call on a GPU looks the array's device address up, which makes the runtime
+ * map it there (it then stays until the process ends): make that first call
+ * outside any graph capture.  The caller passes A, B and C as for
+ * wsmul_mod_p_ex; args->workspace must be NULL (the attached workspace of
+ * wsmul_set_workspace is not used either), and WS_FLAG_CHECK / WS_FLAG_TRACE
+ * are rejected (WS_EINVAL).  A product whose temporaries (rounded up to 256
+ * bytes) plus digit planes exceed the scratch returns WS_ENOMEM before any
+ * launch.  Every call on one GPU uses the same array, which keeps the last
+ * call's contents (no kernel needs it cleared): calls that overlap in time on
+ * one GPU, on any streams, race, so order them.
+ */
+WSMUL_API int wsmul_mod_p_noalloc(const ws_args *args);
+
 /*
  * Bytes of temporaries the schedule needs (its "extra memory": Eq. (1) for
  * Table 1, Eq. (2) for Table 2, the bounds of Sections 5-6 for Tables 4-9,

@@ -24,6 +24,7 @@ WS_FLAG_CHECK, WS_FLAG_NOFUSE, WS_FLAG_TRACE, WS_FLAG_SYNC = 1, 2, 4, 8
  WS_TILE_SK32, WS_TILE_DMA16) = range(7)
 WS_TILE_KINDS = 7
 WS_MAX_IN, WS_MAX_OUT = 8, 6
+WSMUL_NOALLOC_SCRATCH_BYTES = 128 << 20
 WS_BUF_A, WS_BUF_B, WS_BUF_C, WS_BUF_W = 0, 1, 2, 3
 WS_OP_ADD, WS_OP_GEMM = 0, 1
 
@@ -98,6 +99,7 @@ def lib():
             "wsmul_mod_p_i64": (ctypes.c_int, [_i64, _i64, _i64, _i64, _vp, _vp, _vp, _i64,
                                                _i64, ctypes.c_int, ctypes.c_int]),
             "wsmul_mod_p_ex": (ctypes.c_int, [ctypes.POINTER(ws_args)]),
+            "wsmul_mod_p_noalloc": (ctypes.c_int, [ctypes.POINTER(ws_args)]),
             "wsmul_workspace_bytes": (ctypes.c_size_t, [_i64, _i64, _i64, ctypes.c_int,
                                                         ctypes.c_int, ctypes.c_int,
                                                         ctypes.c_int]),
@@ -192,6 +194,10 @@ def make_args(m, k, n, p, A=None, B=None, C=None, alpha=1, beta=0, schedule=WS_T
 
 def wsmul_mod_p_ex(args):
     return lib().wsmul_mod_p_ex(ctypes.byref(args))
+
+
+def wsmul_mod_p_noalloc(args):
+    return lib().wsmul_mod_p_noalloc(ctypes.byref(args))
 
 
 def wsmul_workspace_bytes(m, k, n, dtype, schedule, levels, beta_nonzero):

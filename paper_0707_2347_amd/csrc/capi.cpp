@@ -343,6 +343,75 @@ int execute(const ws_args &a, const PlanKey &key) {
     return rc;
 }
 
+// Scratch of the no-allocation entry point: one file-scope device array per
+// GPU, held from module load until the process ends.  Host code never uses
+// the array's name as an address; it asks the runtime for the device address
+// once per device and passes that pointer to the kernels.
+static __device__ __align__(256) unsigned char scratch[WSMUL_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[64] = {nullptr};
+}
+
+// Device address of this GPU's scratch array (looked up on the first call
+// made with the device current).
+int noalloc_scratch(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return fail(WS_EHIP, "hipGetDevice failed");
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(WS_EHIP, std::string("hipGetSymbolAddress of the static scratch failed: ") +
+                                     hipGetErrorString(e));
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return WS_OK;
+}
+
+// The plan of one product with its workspace and digit scratch carved from
+// the static scratch: no device allocation, no synchronisation.
+int execute_noalloc(const ws_args &a, const PlanKey &key) {
+    std::shared_ptr<Plan> plan;
+    try {
+        plan = get_plan(key);
+    } catch (const std::exception &e) {
+        return fail(WS_EINVAL, std::string("planner: ") + e.what());
+    }
+    hipStream_t stream = a.stream ? static_cast<hipStream_t>(a.stream) : g_stream.load();
+    const size_t ws_bytes = ((size_t)plan->ws_elems * 8u + 255) & ~size_t(255);
+    size_t scratch_bytes = 0;
+    if (a.base == WS_BASE_I8_LIMBS)
+        for (const OpDesc &op : plan->ops)
+            if (op.kind == WS_OP_GEMM)
+                scratch_bytes = std::max(scratch_bytes,
+                                         digit_scratch_bytes(op.a.rows, op.b.cols, op.a.cols));
+    const size_t need = ws_bytes + scratch_bytes;
+    if (need > (size_t)WSMUL_NOALLOC_SCRATCH_BYTES)
+        return fail(WS_ENOMEM, "the product needs " + std::to_string(need) +
+                                   " bytes of workspace and digit scratch; the static scratch of "
+                                   "wsmul_mod_p_noalloc holds " +
+                                   std::to_string((size_t)WSMUL_NOALLOC_SCRATCH_BYTES));
+    void *base = nullptr;
+    const int st = noalloc_scratch(&base);
+    if (st != WS_OK)
+        return st;
+    unsigned char *b = static_cast<unsigned char *>(base);
+    const int rc = run_plan(*plan, a, ws_bytes ? b : nullptr, stream, false,
+                            scratch_bytes ? b + ws_bytes : nullptr, scratch_bytes);
+    fill_stats(*plan, a, g_stats);
+    g_stats.internal_alloc_bytes = 0;
+    g_stats.scratch_bytes = scratch_bytes;
+    g_stats.live_alloc_bytes = g_live_bytes.load();
+    if (g_stats.workspace_bytes > g_stats.peak_temp_bytes)
+        g_stats.peak_temp_bytes = g_stats.workspace_bytes;
+    return rc;
+}
+
 // WS_FLAG_CHECK: every entry of A, B (and C when beta != 0) in [0, p).
 int check_ranges(const ws_args &a, hipStream_t stream) {
     static std::mutex mu;
@@ -392,6 +461,25 @@ int wsmul_mod_p_ex(const ws_args *args) {
         return WS_OK;
     }
     return execute(a, key);
+}
+
+int wsmul_mod_p_noalloc(const ws_args *args) {
+    if (args && (args->workspace || args->workspace_bytes))
+        return fail(WS_EINVAL, "wsmul_mod_p_noalloc takes its workspace from its static scratch; "
+                               "pass no workspace");
+    if (args && (args->flags & (WS_FLAG_CHECK | WS_FLAG_TRACE)))
+        return fail(WS_EINVAL, "wsmul_mod_p_noalloc takes no WS_FLAG_CHECK or WS_FLAG_TRACE");
+    ws_args a;
+    PlanKey key;
+    Resolved res;
+    int rc = prepare(args, a, key, res);
+    if (rc != WS_OK)
+        return rc;
+    if (a.m == 0 || a.n == 0) {
+        g_stats.workspace_bytes = 0;
+        return WS_OK;
+    }
+    return execute_noalloc(a, key);
 }
 
 static int simple_call(int dtype, int64_t m, int64_t k, int64_t n, int64_t p, void *A, void *B,
