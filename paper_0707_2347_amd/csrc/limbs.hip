@@ -7,8 +7,8 @@
 //     A*B = sum_{w=0..4} 2^(8w) * sum_{i+j=w} A_i * B_j,
 // where every digit product is exact in int32: a weight class holds at most
 // three digit products of magnitude <= K * 2^14, below 2^31 for K <= 32768.
-// The epilogue reduces each class mod p, recombines with the residues
-// 2^(8w) mod p, applies alpha and runs the fused addition rows.
+// The epilogue folds the five classes into two exact binary64 sums, reduces
+// them mod p, recombines, applies alpha and runs the fused addition rows.
 //
 // Digits are first written to a scratch area as three int8 planes per
 // operand, each R x Kp with the inner dimension contiguous (B transposed),
@@ -121,7 +121,7 @@ struct DigitParams {
     const int8_t *Ad;          // 3 planes, Mp x Kp
     const int8_t *Bd;          // 3 planes, Np x Kp
     int64_t Mp, Np, Kp;
-    double cw[5];              // 2^(8w) mod p
+    double c24;                // 2^24 mod p
 };
 
 // 128 x 128 output tile per workgroup, 2 x WN waves (wave tiles of 64 x
@@ -250,36 +250,35 @@ __global__ __launch_bounds__(128 * WN) void gemm_digits_kernel(DigitParams D) {
         __syncthreads();
     }
 
-    // Recombine the weight classes into residues, apply alpha, stage through
-    // LDS (two rounds of 64 rows, one per wave row) and run the fused epilogue
-    // on whole rows.  Output layout of the 16 x 16 x 64 int8 op: lane l,
-    // element v holds row 4*(l/16) + v of column l % 16.
+    // Recombine the weight classes into residues, apply alpha, stage the
+    // whole 128 x 128 tile of residues in LDS (128 KB: the operand buffers
+    // are free by now) and run the fused epilogue on whole rows.  Output
+    // layout of the 16 x 16 x 64 int8 op: lane l, element v holds row
+    // 4*(l/16) + v of column l % 16.
+    // With |class| < 2^31, t = c0 + 2^8 c1 + 2^16 c2 (< 2^48) and
+    // u = c3 + 2^8 c4 (< 2^40) are exact in binary64, and the product is
+    // t + 2^24 u: two reductions, a multiply-add by 2^24 mod p, and a third.
+    static_assert(sizeof(lds) >= TILE * TILE * sizeof(double), "tile stage fits the buffers");
     double *stage = reinterpret_cast<double *>(&lds[0][0][0][0]);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (wm == h) {
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < JB; ++j)
 #pragma unroll
-                for (int j = 0; j < JB; ++j)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        double s = 0.0;
-#pragma unroll
-                        for (int w = 0; w < 5; ++w)
-                            s = fma(D.cw[w], mod_reduce((double)acc[w][i][j][v], P.p, P.pinv), s);
-                        const int r = i * 16 + 4 * g + v;
-                        stage[r * TILE + wn * WCOLS + j * 16 + li] = product_residue(P, s);
-                    }
-        }
-        __syncthreads();
-        for (int e = tid; e < 64 * TILE; e += NT) {
-            const int r = e / TILE, c = e % TILE;
-            const int64_t row = m0 + h * 64 + r, col = n0 + c;
-            if (row < P.M && col < P.N)
-                epilogue_apply<T>(P, stage[e], row, col);
-        }
-        __syncthreads();
+            for (int v = 0; v < 4; ++v) {
+                const double t = fma(65536.0, (double)acc[2][i][j][v],
+                                     fma(256.0, (double)acc[1][i][j][v], (double)acc[0][i][j][v]));
+                const double u = fma(256.0, (double)acc[4][i][j][v], (double)acc[3][i][j][v]);
+                const double s = fma(D.c24, mod_reduce(u, P.p, P.pinv), mod_reduce(t, P.p, P.pinv));
+                const int r = wm * 64 + i * 16 + 4 * g + v;
+                stage[r * TILE + wn * WCOLS + j * 16 + li] = product_residue(P, s);
+            }
+    __syncthreads();
+    for (int e = tid; e < TILE * TILE; e += NT) {
+        const int r = e / TILE, c = e % TILE;
+        const int64_t row = m0 + r, col = n0 + c;
+        if (row < P.M && col < P.N)
+            epilogue_apply<T>(P, stage[e], row, col);
     }
 }
 
@@ -328,11 +327,7 @@ hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtyp
     int8_t *Bd = Ad + 3 * D.Mp * D.Kp;
     D.Ad = Ad;
     D.Bd = Bd;
-    int64_t pw = 1;
-    for (int w = 0; w < 5; ++w) {
-        D.cw[w] = (double)pw;
-        pw = (pw * 256) % p;
-    }
+    D.c24 = (double)((int64_t(1) << 24) % p);
     const void *Aop = static_cast<const char *>(bufs.ptr[op.a.buf]) + op.a.off * esz;
     const void *Bop = static_cast<const char *>(bufs.ptr[op.b.buf]) + op.b.off * esz;
     const uint32_t blocks_a = (uint32_t)((D.Mp * (D.Kp / 8) + 255) / 256);
