@@ -1,30 +1,33 @@
 """Benchmark: exact Winograd products over Z/pZ on one MI355X.
 
-Default workload (acc_4096_p65521_l3): C <- A*B + C mod 65521 with m = k = n =
-4096, three Winograd levels under the read-only two-temporary accumulating
-schedule (Table 9), binary64 matrix-core base case.  One step is one such
-product on inputs already resident in HBM.  The same workload is also timed
-under the input-overwriting accumulating schedule (Table 6; A and B are
-restored from pristine copies outside the timed window) and as one classical
-product.
+Default workload (t1_16384_p1048573): C = A*B mod 1048573 with m = k = n =
+16384, the largest single-GPU configuration, with schedule, Winograd depth and
+base (binary64 matrix cores or 8-bit digits on the int8 matrix cores) chosen
+by the autotuner.  One step is one such product on inputs already resident in
+HBM.  The same product is also timed as the classical product on both bases,
+as Table 1 at one level on the digit base and as Table 1 at two levels on the
+binary64 base, so the line carries Winograd against classical on each base.
 
 --workload selects one of the other configurations instead:
+  acc_4096_p65521_l3            C <- A*B + C mod 65521, 4096^3, three Winograd levels under
+                                the read-only two-temporary accumulating schedule (Table 9),
+                                binary64 base; against the input-overwriting accumulating
+                                schedule (Table 6; A and B restored from pristine copies
+                                outside the timed window) and classical
   t1_512_p65521_l1_i64          C = A*B mod 65521, 512^3, int64 storage, Table 1, one level
   ipmm_8192x4096x8192_p8388593  C = A*B mod 8388593, Algorithm 2 (read-only, in place),
                                 one level, against Table 1 and classical
-  t1_16384_p1048573             C = A*B mod 1048573, 16384^3, schedule, depth and base
-                                chosen by the autotuner, against the binary64 and 8-bit
-                                digit bases under fixed schedules
   overwrite_8192x16384x8192_p8388593
                                 C = A*B mod 8388593 on the largest shape the paper times,
                                 Algorithm 1 (here Table 3, then Table 6 in the freed block:
                                 no workspace, A and B overwritten and restored from copies
                                 outside the timed window), one level, against classical,
                                 Table 1 and Algorithm 2
-  acc_4096_p65521_blocked       the default product under Section 7.2's blocked accumulation:
-                                C in t x t blocks (--blocks, default 2), each block by t
-                                Table 9 calls of two levels, extra memory below 2(n/t)^2/3;
-                                against unblocked Table 9, the Table 2 base and classical
+  acc_4096_p65521_blocked       the 4096^3 accumulation under Section 7.2's blocked
+                                accumulation: C in t x t blocks (--blocks, default 2), each
+                                block by t Table 9 calls of two levels, extra memory below
+                                2(n/t)^2/3; against unblocked Table 9, the Table 2 base and
+                                classical
   batch_2000                    2000 products, sizes log-uniform in [64, 2048], moduli
                                 from {65521, 1048573, 8388593}, autotuned, one hipGraph
                                 replay of the persistent batched launches
@@ -58,9 +61,9 @@ SCHEDULE_NAMES = {0: "classical", 1: "two temporaries (Table 1 / Table 9)",
                   9: "blocked accumulation over Table 9 (Section 7.2)",
                   10: "overwrite left (Table 4)", 11: "accumulate, overwrite B, rectangular (Table 8)",
                   12: "read-only in place with Table 9 accumulations (Algorithm 2)"}
-WORKLOADS = ("acc_4096_p65521_l3", "t1_512_p65521_l1_i64", "ipmm_8192x4096x8192_p8388593",
-             "t1_16384_p1048573", "overwrite_8192x16384x8192_p8388593", "acc_4096_p65521_blocked",
-             "batch_2000")
+WORKLOADS = ("t1_16384_p1048573", "acc_4096_p65521_l3", "t1_512_p65521_l1_i64",
+             "ipmm_8192x4096x8192_p8388593", "overwrite_8192x16384x8192_p8388593",
+             "acc_4096_p65521_blocked", "batch_2000")
 INPUTS_OF = {"acc_4096_p65521_blocked": "acc_4096_p65521_l3"}   # same product, other schedule
 
 
@@ -71,7 +74,7 @@ def log(msg):
 def kernels_digest():
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels.hip", "gemm_common.hpp", "device.hpp"):
+    for name in ("kernels.hip", "limbs.hip", "gemm_common.hpp", "device.hpp"):
         with open(os.path.join(ROOT, "paper_0707_2347_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -92,6 +95,17 @@ def measured_traffic(workload, gemm_dominant):
     return rec.get(key, {}).get("bytes_per_launch")
 
 
+def measured_split_traffic(workload):
+    """HBM bytes per digit-split launch from the same record, or None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("kernels_digest") != kernels_digest():
+        return None
+    return rec.get("digit_split", {}).get("bytes_per_launch")
+
+
 class Ctx:
     """Device, stream and timing helpers shared by the workloads."""
 
@@ -101,6 +115,7 @@ class Ctx:
         self.torch, self.capi, self.inputs, self.args = torch, capi, inputs, args
         self.dev = torch.device("cuda:0")
         self.stream = torch.cuda.current_stream()
+        self.split_roof = None
 
     def to_dev(self, x, dtype=None):
         t = self.torch.from_numpy(x)
@@ -151,15 +166,18 @@ class Ctx:
             % (tr.gemm_launches, gemm_avg_ms, tr.add_launches, add_avg_ms))
         per_step = {"base_products": round(tr.gemm_ms / ntraced, 4),
                     "additions": round(tr.add_ms / ntraced, 4)}
+        if tr.split_launches:
+            per_step["digit_splits"] = round(tr.split_ms / ntraced, 4)
         gemm_dominant = tr.gemm_ms >= tr.add_ms
         traffic = measured_traffic(self.args.workload, gemm_dominant)
         if gemm_dominant and tr.gemm_launches:
             if int8_ops:
-                # 9 digit products of 2*M*N*K int8 ops each per base product
+                # 9 digit products of 2*M*N*K int8 ops each per base product;
+                # the time is the product kernel's own (the splits are apart)
                 ops = 9.0 * gemm_flops_per
                 ach = ops / (gemm_avg_ms * 1e-3) / 1e12
-                roof = {"bound": "mfma", "kernel": "base product (int8 16x16x64 matrix cores, "
-                        "3 x 3 digit products, digit split included)",
+                roof = {"bound": "mfma", "kernel": "gemm_digits_kernel (int8 16x16x64 matrix "
+                        "cores, 3 x 3 digit products of 2mnk int8 ops each)",
                         "achieved": round(ach, 2), "peak": PEAK_I8_MFMA_TOPS, "unit": "TOP/s",
                         "frac": round(ach / PEAK_I8_MFMA_TOPS, 4), "traffic": traffic,
                         "avg_launch_ms": round(gemm_avg_ms, 5), "int8_ops_per_launch": ops}
@@ -179,6 +197,14 @@ class Ctx:
         counts = {"base_products": int(tr.gemm_launches // ntraced),
                   "addition_groups": int(tr.add_launches // ntraced)}
         add_roof = None
+        if tr.split_launches:
+            gbs = tr.split_bytes / (tr.split_ms * 1e-3) / 1e9
+            self.split_roof = {"bound": "hbm", "kernel": "split_rows/split_cols (digit planes)",
+                               "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                               "frac": round(gbs / PEAK_HBM_GBS, 4),
+                               "traffic": measured_split_traffic(self.args.workload),
+                               "avg_launch_ms": round(tr.split_ms / tr.split_launches, 5),
+                               "bytes_per_launch": tr.split_bytes / tr.split_launches}
         if tr.add_launches:
             gbs = add_bytes_per / (add_avg_ms * 1e-3) / 1e9
             add_roof = {"bound": "hbm", "kernel": "fused addition rows", "achieved": round(gbs, 1),
@@ -186,6 +212,16 @@ class Ctx:
                         "traffic": measured_traffic(self.args.workload, False),
                         "avg_launch_ms": round(add_avg_ms, 5), "bytes_per_launch": add_bytes_per}
         return roof, per_step, counts, add_roof
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline_rows(A, B, C, alpha, beta, p, budget_s=12.0):
@@ -220,7 +256,7 @@ def cpu_baseline_rows(A, B, C, alpha, beta, p, budget_s=12.0):
         reps += 1
     dt = elapsed / reps
     return {"value": round(2.0 * rows * k * n / dt / 1e9, 3), "unit": "Gop/s",
-            "cores": threads, "kind": "oracle",
+            "cores": threads, "cpu": cpu_model(), "kind": "oracle",
             "sample": "rows 0..%d of the same product (%d x %d x %d), %d run(s) of %.3f s"
                       % (rows - 1, rows, k, n, reps, dt)}
 
@@ -335,7 +371,11 @@ def single_product(ctx, name):
     roof, per_step, counts, add_roof = ctx.traced(head, max(1, min(steps, 5)), int8_ops=int8)
     if add_roof is not None and roof["bound"] != "hbm":
         extra["roofline_additions"] = add_roof
+    if ctx.split_roof is not None:
+        extra["roofline_digit_splits"] = ctx.split_roof
     extra["peak_temp_bytes"] = int(stats.workspace_bytes)
+    if stats.scratch_bytes:
+        extra["digit_scratch_bytes"] = int(stats.scratch_bytes)
     if nbytes > 0:
         # Device-measured temporaries: one more call on a workspace filled,
         # with a guard band behind it, by a value that is not a residue.
@@ -369,14 +409,36 @@ def single_product(ctx, name):
                 def before():
                     dA.copy_(A0)
                     dB.copy_(B0)
-            ms = ctx.event_ms(lambda: run(args2), reps, before)
+            if before is None:
+                # the same back-to-back timing as the headline
+                ms = ctx.timed(lambda: run(args2), reps, 1)
+            else:
+                ms = ctx.event_ms(lambda: run(args2), reps, before)
             extra[key] = {"ms_per_step": round(ms, 4),
                           "gops": round(flops / (ms * 1e-3) / 1e9, 2),
                           "peak_temp_bytes": int(nb2)}
+            st2 = capi.wsmul_get_stats()
+            if st2.scratch_bytes:
+                extra[key]["digit_scratch_bytes"] = int(st2.scratch_bytes)
             log("%s: %.3f ms, %.1f Gop/s" % (key, ms, flops / (ms * 1e-3) / 1e9))
             return ms
 
-        cl_ms = compare("classical", capi.WS_CLASSICAL, 0)
+        if name == "t1_16384_p1048573":
+            # Classical on both bases; Winograd (Table 1) on each base at its
+            # best depth; the speed-up is against the faster classical product.
+            cl_f64 = compare("classical_f64", capi.WS_CLASSICAL, 0)
+            cl_i8 = compare("classical_int8_digits", capi.WS_CLASSICAL, 0, capi.WS_BASE_I8_LIMBS)
+            t1_i8 = compare("table1_1_level_int8_digits", capi.WS_TWO_TEMP, 1,
+                            capi.WS_BASE_I8_LIMBS)
+            t1_f64 = compare("table1_2_levels_f64", capi.WS_TWO_TEMP, 2)
+            cl_ms = min(cl_f64, cl_i8)
+            extra["fastest_classical"] = ("classical_int8_digits" if cl_i8 <= cl_f64
+                                          else "classical_f64")
+            extra["winograd_vs_classical_same_base"] = {
+                "f64 (Table 1, 2 levels)": round(cl_f64 / t1_f64, 4),
+                "int8 digits (Table 1, 1 level)": round(cl_i8 / t1_i8, 4)}
+        else:
+            cl_ms = compare("classical", capi.WS_CLASSICAL, 0)
         if name == "acc_4096_p65521_l3":
             compare("overwrite_table6", capi.WS_OVERWRITE, lev, restore=True)
         elif name == "ipmm_8192x4096x8192_p8388593":
@@ -392,10 +454,6 @@ def single_product(ctx, name):
             compare("blocked_t2_table9_1_level", capi.WS_BLOCKED_ACC, 1, blocks=2)
             compare("blocked_t3_table2_1_level", capi.WS_BLOCKED, 1, blocks=3)
             compare("blocked_t4_table9_1_level", capi.WS_BLOCKED_ACC, 1, blocks=4)
-        elif name == "t1_16384_p1048573":
-            compare("classical_int8_digits", capi.WS_CLASSICAL, 0, capi.WS_BASE_I8_LIMBS)
-            compare("table1_1_level_int8_digits", capi.WS_TWO_TEMP, 1, capi.WS_BASE_I8_LIMBS)
-            compare("table1_2_levels_f64", capi.WS_TWO_TEMP, 2)
         extra["speedup_vs_classical"] = round(cl_ms / ms_step, 4)
 
     cpu = None
@@ -468,7 +526,7 @@ def batch_2000(ctx):
             if dt > 12.0:
                 break
         cpu = {"value": round(fl / dt / 1e9, 3), "unit": "Gop/s", "cores": threads,
-               "kind": "oracle", "sample": "the first %d of the 2000 products, %.1f s"
+               "cpu": cpu_model(), "kind": "oracle", "sample": "the first %d of the 2000 products, %.1f s"
                                            % (done, dt)}
     config = {"workload": "batch_2000", "products": len(probs), "sizes": "m, k, n log-uniform "
               "in [64, 2048]", "moduli": list(inputs.PRIMES), "op": "C = A*B",

@@ -233,9 +233,12 @@ WSMUL_API int wsmul_set_stream(void *stream);
  * launch; a traced call waits for its own completion). */
 typedef struct ws_trace {
     uint64_t add_launches, gemm_launches;
-    double add_ms, gemm_ms;
+    double add_ms, gemm_ms;    /* gemm_ms: the product kernels only (digit splits apart) */
     double add_bytes;          /* algorithmic bytes of the addition launches: 8*(nin+nout)*elements */
     double gemm_flops;         /* 2*M*N*K of the base products */
+    uint64_t split_launches;   /* digit base: operand-split kernels                      */
+    double split_ms;
+    double split_bytes;        /* 8 bytes read and 3 written per (padded) operand entry */
 } ws_trace;
 
 WSMUL_API int wsmul_get_stats(ws_stats *out);

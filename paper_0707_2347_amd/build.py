@@ -2,7 +2,9 @@
 
 Every translation unit is compiled with hipcc for --offload-arch=gfx950 with
 packed-FP32 instructions disabled, then linked into one shared library that
-exports only the C-ABI declared in include/wsmul.h.
+exports only the C-ABI declared in include/wsmul.h.  The feature flag reaches
+the host pass too, which warns that it does not know it and ignores it (the
+clang driver forwards no -Xclang argument to the device pass alone).
 """
 import concurrent.futures
 import os
@@ -28,8 +30,9 @@ SOURCES = ["plan.cpp", "capi.cpp", "autotune.cpp", "batch.cpp", "kernels.hip", "
 def _compile(src):
     path = os.path.join(CSRC, src)
     obj = os.path.join(BUILD, src + ".o")
-    lang = ["-x", "hip"] if src.endswith(".hip") else ["-x", "hip"]
-    cmd = [HIPCC] + lang + COMMON + ["-c", path, "-o", obj]
+    # Every unit is HIP: the C++ ones hold host code and the static device
+    # scratch of the no-allocation entry point.
+    cmd = [HIPCC, "-x", "hip"] + COMMON + ["-c", path, "-o", obj]
     subprocess.run(cmd, check=True)
     return obj
 

@@ -59,7 +59,8 @@ class ws_stats(ctypes.Structure):
 
 class ws_trace(ctypes.Structure):
     _fields_ = [("add_launches", _u64), ("gemm_launches", _u64),
-                ("add_ms", _dbl), ("gemm_ms", _dbl), ("add_bytes", _dbl), ("gemm_flops", _dbl)]
+                ("add_ms", _dbl), ("gemm_ms", _dbl), ("add_bytes", _dbl), ("gemm_flops", _dbl),
+                ("split_launches", _u64), ("split_ms", _dbl), ("split_bytes", _dbl)]
 
 
 class ws_view(ctypes.Structure):

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -206,9 +207,11 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
     DevBufs bufs{{a.A, a.B, a.C, ws}, scratch, scratch_bytes};
     // Traced runs: a start/stop event pair per operation, stamped by the
     // kernel dispatches themselves.
+    // The digit base gets a second pair per operation for its splits.
+    const size_t per_op = a.base == WS_BASE_I8_LIMBS ? 4 : 2;
     std::vector<hipEvent_t> ev;
     if (trace) {
-        ev.assign(2 * plan.ops.size(), nullptr);
+        ev.assign(per_op * plan.ops.size(), nullptr);
         for (auto &e : ev)
             if (hipEventCreate(&e) != hipSuccess) {
                 for (auto &d : ev)
@@ -232,7 +235,9 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
             break;
         }
         if (trace)
-            launch_timing() = LaunchTiming{ev[2 * i], ev[2 * i + 1], false};
+            launch_timing() = per_op == 4 ? LaunchTiming{ev[4 * i], ev[4 * i + 1], false,
+                                                         ev[4 * i + 2], ev[4 * i + 3]}
+                                          : LaunchTiming{ev[2 * i], ev[2 * i + 1], false};
         hipError_t err;
         if (op.kind == WS_OP_ADD)
             err = launch_add_rows(op, bufs, a.dtype, a.p, stream);
@@ -249,9 +254,20 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
             rc = fail(WS_EHIP, "hipStreamSynchronize failed");
         for (size_t i = 0; i < plan.ops.size() && rc == WS_OK; ++i) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) != hipSuccess)
+            if (hipEventElapsedTime(&ms, ev[per_op * i], ev[per_op * i + 1]) != hipSuccess)
                 ms = 0.f;   // an operation with no kernel (empty view)
             const OpDesc &op = plan.ops[i];
+            if (per_op == 4 && op.kind == WS_OP_GEMM) {
+                float sms = 0.f;
+                if (hipEventElapsedTime(&sms, ev[4 * i + 2], ev[4 * i + 3]) == hipSuccess) {
+                    const double M = (double)op.a.rows, K = (double)op.a.cols, N = (double)op.b.cols;
+                    const double Mp = std::ceil(M / 128) * 128, Np = std::ceil(N / 128) * 128,
+                                 Kp = std::ceil(std::max(K, 1.0) / 64) * 64;
+                    g_trace.split_launches += 2;
+                    g_trace.split_ms += sms;
+                    g_trace.split_bytes += 8.0 * (M * K + K * N) + 3.0 * (Mp + Np) * Kp;
+                }
+            }
             if (op.kind == WS_OP_ADD) {
                 g_trace.add_launches += 1;
                 g_trace.add_ms += ms;

@@ -13,9 +13,12 @@ namespace wsmul {
 // of this thread stamp `start` when the first kernel begins and `stop` when
 // the last one ends: the dispatch records them, so the interval is the
 // kernels' own execution time, as a kernel-trace profiler reports it.
+// The digit base times its operand splits apart from its product: while
+// `split_start`/`split_stop` are set, the split launches stamp those instead.
 struct LaunchTiming {
     hipEvent_t start = nullptr, stop = nullptr;
     bool started = false;
+    hipEvent_t split_start = nullptr, split_stop = nullptr;
 };
 LaunchTiming &launch_timing();
 

@@ -332,6 +332,10 @@ hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtyp
     const void *Bop = static_cast<const char *>(bufs.ptr[op.b.buf]) + op.b.off * esz;
     const uint32_t blocks_a = (uint32_t)((D.Mp * (D.Kp / 8) + 255) / 256);
     const dim3 grid_b((uint32_t)(D.Kp / 64), (uint32_t)(D.Np / 64));
+    // Traced runs time the splits on their own event pair.
+    const LaunchTiming timing = launch_timing();
+    if (timing.split_start)
+        launch_timing() = LaunchTiming{timing.split_start, timing.split_stop, false, nullptr, nullptr};
     if (dtype == WS_I64) {
         ws_launch(split_rows_kernel<int64_t>, dim3(blocks_a), dim3(256), 0, stream,
                   static_cast<const int64_t *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
@@ -347,6 +351,7 @@ hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtyp
                   static_cast<const double *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
                   P.p, P.half);
     }
+    launch_timing() = timing;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
