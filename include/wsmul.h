@@ -79,8 +79,10 @@ typedef enum {
     WS_BLOCKED_ACC = 9,      /* Section 7.2 over Table 9 (m == k == n, t | n)      */
     WS_OVL = 10,             /* Table 4: C = A*B, one temporary, destroys A (square) */
     WS_ACR = 11,             /* Table 8: any even shape, two temporaries, destroys B */
-    WS_IPMM_ACC = 12         /* Algorithm 2 with Table 9 for the accumulating chunks
+    WS_IPMM_ACC = 12,        /* Algorithm 2 with Table 9 for the accumulating chunks
                                 (end of Section 7.1; beta == 0, k >= n/2)          */
+    WS_ROWS = 13             /* a schedule given as rows (wsmul_register_rows); its
+                                id goes in ws_args.blocks; square shapes, any beta   */
 } ws_schedule;
 
 /*
@@ -185,6 +187,50 @@ WSMUL_API int wsmul_mod_p_i64(int64_t m, int64_t k, int64_t n, int64_t p,
 
 /* Everything explicit (leading dimensions, dtype, base, stream, workspace). */
 WSMUL_API int wsmul_mod_p_ex(const ws_args *args);
+
+/*
+ * Schedules given as data: the rows of one level of a memory schedule, as
+ * the exhaustive search of Section 4 produces them, run by the library at
+ * every level.  A row names blocks of the current call: 0-3 the quadrants
+ * C11, C12, C21, C22 of its C; 4-7 A11, A12, A21, A22 and 8-11 B11..B22
+ * (read only: never a destination); 12 .. 12+ntemps-1 its temporaries, each
+ * the size of a quadrant of C (at most WS_ROW_MAX_TEMPS per call, one set per
+ * call depth in the workspace).
+ *   WS_ROW_ADD: dst <- cx*x + cy*y (an addition row; dst may be x or y);
+ *   WS_ROW_MUL: dst <- sign*alpha*x*y, a recursive plain product (Table 1
+ *               below this level, the classical base at the last);
+ *   WS_ROW_ACC: dst <- sign*alpha*x*y + cs*dst, a recursive call of this same
+ *               schedule with beta' = cs (the classical base at the last).
+ * Coefficients cx, cy, cs are WS_COEF_* codes (1, -1, beta, -beta of the
+ * call); sign is +1 or -1; a product's destination is neither operand.
+ * The library checks the rows' form, not their algebra: a list that does not
+ * compute alpha*A*B + beta*C gives a wrong C (the caller's search or replay
+ * proves it does).  Square shapes only, n divisible by 2^levels.
+ */
+enum { WS_ROW_ADD = 0, WS_ROW_MUL = 1, WS_ROW_ACC = 2 };
+enum { WS_COEF_ONE = 1, WS_COEF_MINUS_ONE = 2, WS_COEF_BETA = 3, WS_COEF_MINUS_BETA = 4 };
+#define WS_ROW_MAX_TEMPS 4
+#define WS_ROW_MAX_ROWS 64
+typedef struct ws_row {
+    int32_t op;
+    int32_t dst, x, y;
+    int32_t cx, cy;
+    int32_t cs, sign;
+} ws_row;
+
+/* Check and register a row schedule (nrows rows, ntemps temporaries per
+ * call); *id receives its id (equal rows give equal ids), to be passed as
+ * ws_args.blocks with schedule WS_ROWS to any entry point (wsmul_mod_p_ex,
+ * wsmul_plan_info, wsmul_batched, ...).  WS_EINVAL for malformed rows.
+ * Registered schedules live until the process ends. */
+WSMUL_API int wsmul_register_rows(const ws_row *rows, int nrows, int ntemps, int *id);
+
+/* Register and run in one call: C <- (alpha*A*B + beta*C) mod p under the
+ * row schedule with args->levels levels; the other fields of args as for
+ * wsmul_mod_p_ex (args->schedule and args->blocks are ignored).  WS_EINVAL
+ * for malformed rows, WS_ESHAPE for non-square shapes or n not divisible by
+ * 2^levels; A and B are read only. */
+WSMUL_API int wsmul_mod_p_rows(const ws_args *args, const ws_row *rows, int nrows, int ntemps);
 
 /* Size of the static device scratch of wsmul_mod_p_noalloc, per GPU. */
 #define WSMUL_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)

@@ -25,6 +25,10 @@ WS_FLAG_CHECK, WS_FLAG_NOFUSE, WS_FLAG_TRACE, WS_FLAG_SYNC = 1, 2, 4, 8
 WS_TILE_KINDS = 7
 WS_MAX_IN, WS_MAX_OUT = 8, 6
 WSMUL_NOALLOC_SCRATCH_BYTES = 128 << 20
+WS_ROWS = 13
+WS_ROW_ADD, WS_ROW_MUL, WS_ROW_ACC = 0, 1, 2
+WS_COEF_ONE, WS_COEF_MINUS_ONE, WS_COEF_BETA, WS_COEF_MINUS_BETA = 1, 2, 3, 4
+WS_ROW_MAX_TEMPS, WS_ROW_MAX_ROWS = 4, 64
 WS_BUF_A, WS_BUF_B, WS_BUF_C, WS_BUF_W = 0, 1, 2, 3
 WS_OP_ADD, WS_OP_GEMM = 0, 1
 
@@ -55,6 +59,11 @@ class ws_stats(ctypes.Structure):
                 ("base_flops", _u64), ("rows", _u64), ("levels", _u64),
                 ("schedule", _i64), ("base", _i64), ("scratch_bytes", _u64),
                 ("batch_phases", _u64), ("live_alloc_bytes", _u64)]
+
+
+class ws_row(ctypes.Structure):
+    _fields_ = [("op", _i32), ("dst", _i32), ("x", _i32), ("y", _i32),
+                ("cx", _i32), ("cy", _i32), ("cs", _i32), ("sign", _i32)]
 
 
 class ws_trace(ctypes.Structure):
@@ -101,6 +110,10 @@ def lib():
                                                _i64, ctypes.c_int, ctypes.c_int]),
             "wsmul_mod_p_ex": (ctypes.c_int, [ctypes.POINTER(ws_args)]),
             "wsmul_mod_p_noalloc": (ctypes.c_int, [ctypes.POINTER(ws_args)]),
+            "wsmul_mod_p_rows": (ctypes.c_int, [ctypes.POINTER(ws_args), ctypes.POINTER(ws_row),
+                                                ctypes.c_int, ctypes.c_int]),
+            "wsmul_register_rows": (ctypes.c_int, [ctypes.POINTER(ws_row), ctypes.c_int,
+                                                   ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
             "wsmul_workspace_bytes": (ctypes.c_size_t, [_i64, _i64, _i64, ctypes.c_int,
                                                         ctypes.c_int, ctypes.c_int,
                                                         ctypes.c_int]),
@@ -195,6 +208,27 @@ def make_args(m, k, n, p, A=None, B=None, C=None, alpha=1, beta=0, schedule=WS_T
 
 def wsmul_mod_p_ex(args):
     return lib().wsmul_mod_p_ex(ctypes.byref(args))
+
+
+def make_rows(rows):
+    """A ctypes array of ws_row from (op, dst, x, y, cx, cy, cs, sign) tuples."""
+    arr = (ws_row * len(rows))()
+    for r, t in zip(arr, rows):
+        r.op, r.dst, r.x, r.y, r.cx, r.cy, r.cs, r.sign = t
+    return arr
+
+
+def wsmul_mod_p_rows(args, rows, ntemps):
+    arr = rows if isinstance(rows, ctypes.Array) else make_rows(rows)
+    return lib().wsmul_mod_p_rows(ctypes.byref(args), arr, len(arr), ntemps)
+
+
+def wsmul_register_rows(rows, ntemps):
+    """Return (status, id) of a registered row schedule."""
+    arr = rows if isinstance(rows, ctypes.Array) else make_rows(rows)
+    out = ctypes.c_int(0)
+    st = lib().wsmul_register_rows(arr, len(arr), ntemps, ctypes.byref(out))
+    return st, out.value
 
 
 def wsmul_mod_p_noalloc(args):

@@ -126,9 +126,11 @@ int prepare(const ws_args *in, ws_args &a, PlanKey &key, Resolved &res) {
     if (a.base != WS_BASE_AUTO && a.base != WS_BASE_F64_MFMA && a.base != WS_BASE_I8_LIMBS)
         return fail(WS_EINVAL, "unknown base kind");
     const bool beta_nz = canon(a.beta, a.p) != 0;
-    if (a.blocks == 0)
+    if (a.blocks == 0 && a.schedule != WS_ROWS)
         a.blocks = 2;
-    if (a.schedule == WS_AUTO || a.levels < 0 || a.base == WS_BASE_AUTO) {
+    if (a.schedule == WS_ROWS && a.levels < 0)
+        return fail(WS_EINVAL, "a row schedule needs levels >= 0");
+    if (a.schedule != WS_ROWS && (a.schedule == WS_AUTO || a.levels < 0 || a.base == WS_BASE_AUTO)) {
         const int rc = autotune_choice(a, beta_nz);
         if (rc != WS_OK)
             return rc;
@@ -157,7 +159,10 @@ int prepare(const ws_args *in, ws_args &a, PlanKey &key, Resolved &res) {
     key.table = res.table;
     key.levels = res.levels;
     key.fuse = (a.flags & WS_FLAG_NOFUSE) ? 0 : 1;
-    key.blocks = (res.table == TAB_BLOCKED_HL || res.table == TAB_BLOCKED_ACC) ? (int32_t)a.blocks : 0;
+    key.blocks = (res.table == TAB_BLOCKED_HL || res.table == TAB_BLOCKED_ACC ||
+                  res.table == TAB_ROWS) ? (int32_t)a.blocks : 0;
+    if (res.table == TAB_ROWS && !rows_registered(key.blocks))
+        return fail(WS_ESCHEDULE, "WS_ROWS runs a schedule registered by wsmul_mod_p_rows");
     return WS_OK;
 }
 
@@ -470,6 +475,39 @@ int wsmul_mod_p_ex(const ws_args *args) {
     PlanKey key;
     Resolved res;
     int rc = prepare(args, a, key, res);
+    if (rc != WS_OK)
+        return rc;
+    if (a.m == 0 || a.n == 0) {
+        g_stats.workspace_bytes = 0;
+        return WS_OK;
+    }
+    return execute(a, key);
+}
+
+int wsmul_register_rows(const ws_row *rows, int nrows, int ntemps, int *id) {
+    if (!id)
+        return fail(WS_EINVAL, "null id");
+    std::string err;
+    *id = register_rows(rows, nrows, ntemps, &err);
+    if (*id == 0)
+        return fail(WS_EINVAL, "row schedule: " + err);
+    return WS_OK;
+}
+
+int wsmul_mod_p_rows(const ws_args *args, const ws_row *rows, int nrows, int ntemps) {
+    if (!args)
+        return fail(WS_EINVAL, "null argument block");
+    std::string err;
+    const int id = register_rows(rows, nrows, ntemps, &err);
+    if (id == 0)
+        return fail(WS_EINVAL, "row schedule: " + err);
+    ws_args r = *args;
+    r.schedule = WS_ROWS;
+    r.blocks = (uint32_t)id;
+    ws_args a;
+    PlanKey key;
+    Resolved res;
+    int rc = prepare(&r, a, key, res);
     if (rc != WS_OK)
         return rc;
     if (a.m == 0 || a.n == 0) {

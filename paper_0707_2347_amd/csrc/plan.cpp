@@ -11,7 +11,10 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
+#include <string>
+#include <vector>
 
 namespace wsmul {
 
@@ -233,6 +236,23 @@ class Fuser {
 };
 
 // --------------------------------------------------------------- emitter
+// Registered row schedules (index + 1 is the id); never removed.
+struct RowSchedule {
+    std::vector<ws_row> rows;
+    int ntemps;
+};
+std::mutex g_rows_mu;
+std::vector<RowSchedule> g_row_schedules;
+
+bool row_schedule(int id, std::vector<ws_row> &rows, int &ntemps) {
+    std::lock_guard<std::mutex> lock(g_rows_mu);
+    if (id < 1 || id > (int)g_row_schedules.size())
+        return false;
+    rows = g_row_schedules[(size_t)id - 1].rows;
+    ntemps = g_row_schedules[(size_t)id - 1].ntemps;
+    return true;
+}
+
 class Emitter {
   public:
     Emitter(int64_t p, bool measure, bool fuse, std::vector<OpDesc> &ops)
@@ -264,7 +284,7 @@ class Emitter {
 
     // ---- temporaries
     struct Frame {
-        View v[3];
+        View v[WS_ROW_MAX_TEMPS > 3 ? WS_ROW_MAX_TEMPS : 3];
         bool region = false;
     };
     // Temporaries of one call at call depth d.  Normally they are carved from
@@ -274,10 +294,15 @@ class Emitter {
     // bottom-left, third in the top-right, and the bottom-right is lent on to
     // the callees.
     Frame frame(int d, std::initializer_list<std::pair<int64_t, int64_t>> shapes) {
+        return frame(d, std::vector<std::pair<int64_t, int64_t>>(shapes));
+    }
+    Frame frame(int d, const std::vector<std::pair<int64_t, int64_t>> &shapes) {
         Frame f;
         if (!regions_.empty()) {
             const View R = regions_.back();
             const View slot[3] = {quad(R, 0, 0), quad(R, 1, 0), quad(R, 0, 1)};
+            if (shapes.size() > 3)
+                throw std::logic_error("a lent region hosts at most three temporaries");
             int i = 0;
             for (auto &s : shapes) {
                 if (s.first > slot[i].rows || s.second > slot[i].cols)
@@ -694,6 +719,46 @@ class Emitter {
         release(f);
     }
 
+    // ---- A schedule given as rows (one level; products recurse as Table 1,
+    // accumulating products into this same schedule).
+    void rowsched(View A, View B, View C, int64_t a, int64_t b, int lev, int d,
+                  const std::vector<ws_row> &rows, int ntemps) {
+        if (lev == 0)
+            return gemm(A, B, C, a, b);
+        depth_ = d;
+        View blk[12 + WS_ROW_MAX_TEMPS];
+        for (int q = 0; q < 4; ++q) {
+            blk[q] = quad(C, q / 2, q % 2);
+            blk[4 + q] = quad(A, q / 2, q % 2);
+            blk[8 + q] = quad(B, q / 2, q % 2);
+        }
+        const int64_t h = C.rows / 2;
+        Frame f = frame(d, std::vector<std::pair<int64_t, int64_t>>((size_t)ntemps, {h, h}));
+        for (int i = 0; i < ntemps; ++i)
+            blk[12 + i] = f.v[i];
+        auto coef = [&](int c) -> int64_t {
+            switch (c) {
+            case WS_COEF_ONE: return 1;
+            case WS_COEF_MINUS_ONE: return p_ - 1;
+            case WS_COEF_BETA: return b % p_;
+            default: return neg(b);
+            }
+        };
+        for (const ws_row &r : rows) {
+            const int64_t sa = r.sign > 0 ? a : neg(a);
+            if (r.op == WS_ROW_ADD) {
+                lin(blk[r.dst], {{coef(r.cx), blk[r.x]}, {coef(r.cy), blk[r.y]}});
+            } else if (r.op == WS_ROW_MUL) {
+                t1(blk[r.x], blk[r.y], blk[r.dst], sa, lev - 1, d + 1);
+                depth_ = d;
+            } else {
+                rowsched(blk[r.x], blk[r.y], blk[r.dst], sa, coef(r.cs), lev - 1, d + 1, rows, ntemps);
+                depth_ = d;
+            }
+        }
+        release(f);
+    }
+
     // ---- Algorithm 2: C <- a*A*B with no extra memory, A and B read only.
     // At depth dd < L the three quadrant products run as Table 1 (first
     // inner chunk) and Table 2 (the other chunks; Table 9 with acc_base, for
@@ -878,6 +943,14 @@ void run(Emitter &e, const PlanKey &key) {
     case TAB_BLOCKED_ACC:
         e.blocked(key.table == TAB_BLOCKED_ACC, A, B, C, a, b, key.blocks, L);
         break;
+    case TAB_ROWS: {
+        std::vector<ws_row> rows;
+        int ntemps = 0;
+        if (!row_schedule(key.blocks, rows, ntemps))
+            throw std::logic_error("unknown row schedule");
+        e.rowsched(A, B, C, a, b, L, 0, rows, ntemps);
+        break;
+    }
     default:
         throw std::logic_error("unknown table");
     }
@@ -885,6 +958,66 @@ void run(Emitter &e, const PlanKey &key) {
 }
 
 }  // namespace
+
+int register_rows(const ws_row *rows, int nrows, int ntemps, std::string *error) {
+    auto bad = [&](const std::string &m) {
+        if (error)
+            *error = m;
+        return 0;
+    };
+    if (!rows || nrows < 1 || nrows > WS_ROW_MAX_ROWS)
+        return bad("a row schedule has 1 to WS_ROW_MAX_ROWS rows");
+    if (ntemps < 0 || ntemps > WS_ROW_MAX_TEMPS)
+        return bad("a row schedule has 0 to WS_ROW_MAX_TEMPS temporaries");
+    const int nblk = 12 + ntemps;
+    auto coef_ok = [](int c) { return c >= WS_COEF_ONE && c <= WS_COEF_MINUS_BETA; };
+    for (int i = 0; i < nrows; ++i) {
+        const ws_row &r = rows[i];
+        const std::string at = " (row " + std::to_string(i) + ")";
+        if (r.dst < 0 || r.dst >= nblk || r.x < 0 || r.x >= nblk || r.y < 0 || r.y >= nblk)
+            return bad("block id out of range" + at);
+        if (r.dst >= 4 && r.dst < 12)
+            return bad("A and B are read only" + at);
+        if (r.op == WS_ROW_ADD) {
+            if (!coef_ok(r.cx) || !coef_ok(r.cy))
+                return bad("unknown coefficient code" + at);
+        } else if (r.op == WS_ROW_MUL || r.op == WS_ROW_ACC) {
+            if (r.sign != 1 && r.sign != -1)
+                return bad("a product's sign is +1 or -1" + at);
+            if (r.dst == r.x || r.dst == r.y)
+                return bad("a product cannot land on its own operand" + at);
+            if (r.op == WS_ROW_ACC && !coef_ok(r.cs))
+                return bad("unknown coefficient code" + at);
+        } else {
+            return bad("unknown row kind" + at);
+        }
+    }
+    std::vector<ws_row> v(rows, rows + nrows);
+    for (ws_row &r : v) {      // fields a row kind does not use compare equal
+        if (r.op != WS_ROW_ADD)
+            r.cx = r.cy = 0;
+        if (r.op != WS_ROW_ACC)
+            r.cs = 0;
+        if (r.op == WS_ROW_ADD)
+            r.sign = 0;
+    }
+    std::lock_guard<std::mutex> lock(g_rows_mu);
+    for (size_t i = 0; i < g_row_schedules.size(); ++i) {
+        const RowSchedule &s = g_row_schedules[i];
+        if (s.ntemps == ntemps && s.rows.size() == v.size() &&
+            std::memcmp(s.rows.data(), v.data(), v.size() * sizeof(ws_row)) == 0)
+            return (int)i + 1;
+    }
+    if (g_row_schedules.size() >= 4096)
+        return bad("too many distinct row schedules registered");
+    g_row_schedules.push_back(RowSchedule{v, ntemps});
+    return (int)g_row_schedules.size();
+}
+
+bool rows_registered(int id) {
+    std::lock_guard<std::mutex> lock(g_rows_mu);
+    return id >= 1 && id <= (int)g_row_schedules.size();
+}
 
 std::vector<int64_t> block_parts(int64_t d, int t, int L) {
     std::vector<int64_t> out;
@@ -975,6 +1108,11 @@ Resolved resolve_schedule(int schedule, int64_t m, int64_t k, int64_t n, bool be
             shape_error("Algorithm 2 with Table 9 needs the shapes of Algorithm 2 and k >= n/2 "
                         "(square chunks)");
         }
+        break;
+    case WS_ROWS:
+        r.table = TAB_ROWS;
+        if (!square || !divisible)
+            shape_error("a row schedule needs m == k == n divisible by 2^levels");
         break;
     case WS_OVL:
         r.table = TAB_OVL;

@@ -37,6 +37,7 @@ enum Table : int {
     TAB_IPMM_ACC = 15,  // Algorithm 2 with Table 9 accumulations
     TAB_BLOCKED_HL = 13,   // Section 7.2, t x t blocks over Table 2
     TAB_BLOCKED_ACC = 14,  // Section 7.2, t x t blocks over Table 9
+    TAB_ROWS = 16,         // a schedule given as rows (PlanKey::blocks holds its id)
 };
 
 struct PlanKey {
@@ -78,6 +79,11 @@ int64_t workspace_elems(int table, int64_t m, int64_t k, int64_t n, int levels, 
 // Lengths of the consecutive parts of one dimension of length d in the
 // blocked accumulation with t blocks per dimension and depth L.
 std::vector<int64_t> block_parts(int64_t d, int t, int L);
+
+// Row schedules: validate and register one (returns an id >= 1, or 0 with
+// *error set); ids of equal row lists are equal.
+int register_rows(const ws_row *rows, int nrows, int ntemps, std::string *error);
+bool rows_registered(int id);
 
 bool ipmm_supported(int64_t m, int64_t k, int64_t n, int levels);
 bool ip0vmm_supported(int64_t m, int64_t k, int64_t n, int levels);
