@@ -7,9 +7,9 @@
 //     whole 128 x 128 tiles, 58 (50) for ragged large products, 45 / 30
 //     TFLOP/s for the 64 x 64 class with whole / ragged tiles, 25 / 19 for
 //     the small class, 7 us floor per launch;
-//   base products, 8-bit digits: 300 / 265 / 180 / 120 / 40 TFLOP/s
-//     (equivalent) by 128 x 128 tile count, plus the digit split passes
-//     (bytes at 5 TB/s);
+//   base products, 8-bit digits: 315 / 295 / 255 / 210 / 45 TFLOP/s
+//     (equivalent) by 128 x 128 tile count (16384^3, 8192^3, 4096^3, 2048^3,
+//     1024^3 measured), plus the digit split passes (bytes at 5.5 TB/s);
 //   addition groups: bytes moved at 4.5 TB/s, 4 us floor per launch.
 // The cheapest candidate whose temporaries fit the memory budget wins.
 // Overwriting schedules are never chosen automatically (they destroy A, B).
@@ -52,13 +52,13 @@ double gemm_f64_us(int64_t M, int64_t N, int64_t K, int64_t p) {
 double gemm_digits_us(int64_t M, int64_t N, int64_t K) {
     const double flops = 2.0 * (double)M * (double)N * (double)K;
     const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
-    const double rate = tiles >= 8192   ? 300e12
-                        : tiles >= 2048 ? 265e12
-                        : tiles >= 512  ? 180e12
-                        : tiles >= 128  ? 120e12
-                                        : 40e12;
+    const double rate = tiles >= 8192   ? 315e12
+                        : tiles >= 2048 ? 295e12
+                        : tiles >= 512  ? 255e12
+                        : tiles >= 128  ? 210e12
+                                        : 45e12;
     const double split_bytes = 11.0 * ((double)M * (double)K + (double)K * (double)N);
-    return std::max(8.0, flops / rate * 1e6) + 2.0 * 5.0 + split_bytes / 5e12 * 1e6;
+    return std::max(8.0, flops / rate * 1e6) + 2.0 * 5.0 + split_bytes / 5.5e12 * 1e6;
 }
 
 struct Key {
