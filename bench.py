@@ -459,7 +459,11 @@ def single_product(ctx, name):
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline_rows(A, B, C, alpha, beta, p)
-    return line(ctx, value, ms_step, "int64" if i64 else "f64", config, roof, cpu, extra)
+    # the arithmetic type: 8-bit digit products (int32 sums) on the digit base
+    dtype = "i8" if config.get("base", "").startswith("int8") else ("int64" if i64 else "f64")
+    if dtype == "i8":
+        config["storage"] = "int64" if i64 else "f64"
+    return line(ctx, value, ms_step, dtype, config, roof, cpu, extra)
 
 
 def batch_2000(ctx):

@@ -285,6 +285,8 @@ typedef struct ws_trace {
     uint64_t split_launches;   /* digit base: operand-split kernels                      */
     double split_ms;
     double split_bytes;        /* 8 bytes read and 3 written per (padded) operand entry */
+    uint64_t digit_adds;       /* digit base: addition groups reading or writing digit planes */
+    uint64_t unsplit_operands; /* digit base: product operands read as planes, not split     */
 } ws_trace;
 
 WSMUL_API int wsmul_get_stats(ws_stats *out);
@@ -384,9 +386,25 @@ enum { WS_OP_ADD = 0, WS_OP_GEMM = 1 };
 
 typedef struct ws_view {
     int32_t buf;               /* WS_BUF_*                                 */
-    int32_t pad;
+    int32_t form;              /* WS_FORM_*: how the view's block holds its values */
     int64_t off, rows, cols, ld;  /* element offset, shape, leading dim   */
 } ws_view;
+
+/* A view holds residues (one storage-type entry per element) unless the
+ * plan runs on the 8-bit digit base: there a workspace temporary that is
+ * written by an addition group and read only by base products (in one
+ * operand role) and by addition groups may hold the three signed digit
+ * planes of its centred residues instead, in the layout the product reads
+ * (rows of 128 x 64 tiles, the inner index contiguous, 16-byte chunks
+ * XOR-swizzled by row; B operands transposed), 3 bytes per element at the
+ * start of its block.  Such a view is dense (ld == cols), even-offset, has
+ * whole tiles (A role: rows % 128 == 0, cols % 64 == 0; B role:
+ * cols % 128 == 0, rows % 64 == 0) and is never read as residues before
+ * something rewrites it.  The forms appear in wsmul_plan_export's output
+ * for the digit base (the execution list it runs); epilogue rows that do
+ * not read the product may be moved there into an addition group of their
+ * own just before it. */
+enum { WS_FORM_RESIDUES = 0, WS_FORM_DIGITS_A = 1, WS_FORM_DIGITS_B = 2 };
 
 /* out[o] <- sum_i coef[o][i] * in[i]  (mod p), elementwise.  For a base
  * product, in[0] stands for alpha*a*b (already reduced) and is not read. */
@@ -405,7 +423,9 @@ typedef struct ws_op_desc {
 WSMUL_API int wsmul_plan_info(const ws_args *args, ws_stats *stats);
 
 /* Copy up to `cap` operations of the plan into `ops`; *count receives the
- * total number (call with cap = 0 to size the buffer). */
+ * total number (call with cap = 0 to size the buffer).  On the digit base
+ * (args->base, or the base the autotuner picks) this is the execution list,
+ * with view forms as described at ws_view. */
 WSMUL_API int wsmul_plan_export(const ws_args *args, ws_op_desc *ops, int64_t cap, int64_t *count);
 
 #ifdef __cplusplus

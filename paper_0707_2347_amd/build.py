@@ -24,7 +24,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
           "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
           "-Wall", "-Wno-unused-result", "-fvisibility=hidden"]
 
-SOURCES = ["plan.cpp", "capi.cpp", "autotune.cpp", "batch.cpp", "kernels.hip", "limbs.hip"]
+SOURCES = ["plan.cpp", "capi.cpp", "autotune.cpp", "batch.cpp", "digit_temps.cpp", "kernels.hip",
+           "limbs.hip"]
 
 
 def _compile(src):

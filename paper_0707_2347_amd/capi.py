@@ -31,6 +31,7 @@ WS_COEF_ONE, WS_COEF_MINUS_ONE, WS_COEF_BETA, WS_COEF_MINUS_BETA = 1, 2, 3, 4
 WS_ROW_MAX_TEMPS, WS_ROW_MAX_ROWS = 4, 64
 WS_BUF_A, WS_BUF_B, WS_BUF_C, WS_BUF_W = 0, 1, 2, 3
 WS_OP_ADD, WS_OP_GEMM = 0, 1
+WS_FORM_RESIDUES, WS_FORM_DIGITS_A, WS_FORM_DIGITS_B = 0, 1, 2
 
 SCHEDULES = {"classical": WS_CLASSICAL, "two_temp": WS_TWO_TEMP, "overwrite": WS_OVERWRITE,
              "readonly_inplace": WS_READONLY_INPLACE, "hl_three_temp": WS_HL_THREE_TEMP,
@@ -69,11 +70,12 @@ class ws_row(ctypes.Structure):
 class ws_trace(ctypes.Structure):
     _fields_ = [("add_launches", _u64), ("gemm_launches", _u64),
                 ("add_ms", _dbl), ("gemm_ms", _dbl), ("add_bytes", _dbl), ("gemm_flops", _dbl),
-                ("split_launches", _u64), ("split_ms", _dbl), ("split_bytes", _dbl)]
+                ("split_launches", _u64), ("split_ms", _dbl), ("split_bytes", _dbl),
+                ("digit_adds", _u64), ("unsplit_operands", _u64)]
 
 
 class ws_view(ctypes.Structure):
-    _fields_ = [("buf", _i32), ("pad", _i32), ("off", _i64), ("rows", _i64),
+    _fields_ = [("buf", _i32), ("form", _i32), ("off", _i64), ("rows", _i64),
                 ("cols", _i64), ("ld", _i64)]
 
 

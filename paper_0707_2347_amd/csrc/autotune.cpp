@@ -7,10 +7,15 @@
 //     whole 128 x 128 tiles, 58 (50) for ragged large products, 45 / 30
 //     TFLOP/s for the 64 x 64 class with whole / ragged tiles, 25 / 19 for
 //     the small class, 7 us floor per launch;
-//   base products, 8-bit digits: 315 / 295 / 255 / 210 / 45 TFLOP/s
+//   base products, 8-bit digits: 305 / 295 / 255 / 210 / 45 TFLOP/s
 //     (equivalent) by 128 x 128 tile count (16384^3, 8192^3, 4096^3, 2048^3,
-//     1024^3 measured), plus the digit split passes (bytes at 5.5 TB/s);
-//   addition groups: bytes moved at 4.5 TB/s, 4 us floor per launch.
+//     1024^3 measured, the product's store included; other epilogue streams
+//     at 10 TB/s, as they mostly overlap other tiles' products), plus the
+//     digit split passes of operands that are not already digit planes
+//     (bytes at 5.5 TB/s);
+//   addition groups: bytes moved at 4.5 TB/s (5.0 TB/s for the digit base's
+//     groups on digit-plane temporaries, 3 bytes per such entry), 4 us floor
+//     per launch.
 // The cheapest candidate whose temporaries fit the memory budget wins.
 // Overwriting schedules are never chosen automatically (they destroy A, B).
 // For accumulating products the blocked accumulation of Section 7.2 (t = 2,
@@ -49,16 +54,18 @@ double gemm_f64_us(int64_t M, int64_t N, int64_t K, int64_t p) {
     return std::max(7.0, flops / rate * 1e6);
 }
 
-double gemm_digits_us(int64_t M, int64_t N, int64_t K) {
+double gemm_digits_us(int64_t M, int64_t N, int64_t K, bool pre_a = false, bool pre_b = false) {
     const double flops = 2.0 * (double)M * (double)N * (double)K;
     const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
-    const double rate = tiles >= 8192   ? 315e12
+    const double rate = tiles >= 8192   ? 305e12
                         : tiles >= 2048 ? 295e12
                         : tiles >= 512  ? 255e12
                         : tiles >= 128  ? 210e12
                                         : 45e12;
-    const double split_bytes = 11.0 * ((double)M * (double)K + (double)K * (double)N);
-    return std::max(8.0, flops / rate * 1e6) + 2.0 * 5.0 + split_bytes / 5.5e12 * 1e6;
+    const double split_bytes = 11.0 * ((pre_a ? 0.0 : (double)M * (double)K) +
+                                       (pre_b ? 0.0 : (double)K * (double)N));
+    const int splits = (pre_a ? 0 : 1) + (pre_b ? 0 : 1);
+    return std::max(8.0, flops / rate * 1e6) + 5.0 * splits + split_bytes / 5.5e12 * 1e6;
 }
 
 struct Key {
@@ -242,6 +249,29 @@ bool search(const Key &key, Choice &best, Resolved *reject) {
 
 double plan_cost_us(const Plan &plan, int base) {
     double t = 0.0;
+    if (base == WS_BASE_I8_LIMBS) {
+        // the digit base's execution list: temporaries held as digit planes
+        // move 3 bytes per entry and spare their products' splits
+        for (const ExecOp &e : *digit_exec(plan)) {
+            const OpDesc &op = e.op;
+            const double elems = (double)op.out[0].rows * (double)op.out[0].cols;
+            if (op.kind == WS_OP_GEMM) {
+                // the rates include the product's own store; further epilogue
+                // streams mostly overlap other tiles' products (~10 TB/s)
+                t += gemm_digits_us(op.a.rows, op.b.cols, op.a.cols, e.pre_a, e.pre_b);
+                t += 8.0 * (double)(op.nin - 1 + op.nout - 1) * elems / 10e12 * 1e6;
+            } else {
+                double per = 0.0;
+                for (int i = 0; i < op.nin; ++i)
+                    per += e.in_enc[i] ? 3.0 : 8.0;
+                for (int o = 0; o < op.nout; ++o)
+                    per += e.out_enc[o] ? 3.0 : 8.0;
+                const bool digits = exec_uses_digits(e);
+                t += std::max(4.0, per * elems / (digits ? 5.0e12 : 4.5e12) * 1e6);
+            }
+        }
+        return t;
+    }
     for (const OpDesc &op : plan.ops) {
         if (op.kind == WS_OP_GEMM) {
             t += base == WS_BASE_I8_LIMBS ? gemm_digits_us(op.a.rows, op.b.cols, op.a.cols)

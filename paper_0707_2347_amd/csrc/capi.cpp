@@ -214,9 +214,21 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
     // kernel dispatches themselves.
     // The digit base gets a second pair per operation for its splits.
     const size_t per_op = a.base == WS_BASE_I8_LIMBS ? 4 : 2;
+    // The digit base runs the plan's execution list, in which temporaries
+    // that only feed base products and addition groups stay digit planes.
+    std::shared_ptr<const std::vector<ExecOp>> dexec;
+    if (a.base == WS_BASE_I8_LIMBS && ws && reinterpret_cast<uintptr_t>(ws) % 16 == 0) {
+        try {
+            dexec = digit_exec(plan);
+        } catch (const std::exception &e) {
+            return fail(WS_ENOMEM, std::string("digit execution list: ") + e.what());
+        }
+    }
+    const size_t nops = dexec ? dexec->size() : plan.ops.size();
+    auto op_at = [&](size_t i) -> const OpDesc & { return dexec ? (*dexec)[i].op : plan.ops[i]; };
     std::vector<hipEvent_t> ev;
     if (trace) {
-        ev.assign(per_op * plan.ops.size(), nullptr);
+        ev.assign(per_op * nops, nullptr);
         for (auto &e : ev)
             if (hipEventCreate(&e) != hipSuccess) {
                 for (auto &d : ev)
@@ -232,8 +244,8 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
     if (const char *f = std::getenv("WSMUL_FAULT_AT"))
         fault_at = std::strtol(f, nullptr, 10);
     int rc = WS_OK;
-    for (size_t i = 0; i < plan.ops.size() && rc == WS_OK; ++i) {
-        const OpDesc &op = plan.ops[i];
+    for (size_t i = 0; i < nops && rc == WS_OK; ++i) {
+        const OpDesc &op = op_at(i);
         if (fault_at >= 0 && (size_t)fault_at == i) {
             rc = fail(WS_EHIP, "injected failure before operation " + std::to_string(i) +
                                    " (WSMUL_FAULT_AT)");
@@ -245,9 +257,12 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
                                           : LaunchTiming{ev[2 * i], ev[2 * i + 1], false};
         hipError_t err;
         if (op.kind == WS_OP_ADD)
-            err = launch_add_rows(op, bufs, a.dtype, a.p, stream);
+            err = dexec && exec_uses_digits((*dexec)[i])
+                      ? launch_exec_add((*dexec)[i], bufs, a.dtype, a.p, stream)
+                      : launch_add_rows(op, bufs, a.dtype, a.p, stream);
         else if (a.base == WS_BASE_I8_LIMBS)
-            err = launch_gemm_limbs(op, bufs, a.dtype, a.p, stream);
+            err = launch_gemm_limbs(op, bufs, a.dtype, a.p, stream, dexec && (*dexec)[i].pre_a,
+                                    dexec && (*dexec)[i].pre_b);
         else
             err = launch_gemm(op, bufs, a.dtype, a.p, stream);
         if (err != hipSuccess)
@@ -257,27 +272,37 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
     if (trace) {
         if (rc == WS_OK && hipStreamSynchronize(stream) != hipSuccess)
             rc = fail(WS_EHIP, "hipStreamSynchronize failed");
-        for (size_t i = 0; i < plan.ops.size() && rc == WS_OK; ++i) {
+        for (size_t i = 0; i < nops && rc == WS_OK; ++i) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, ev[per_op * i], ev[per_op * i + 1]) != hipSuccess)
                 ms = 0.f;   // an operation with no kernel (empty view)
-            const OpDesc &op = plan.ops[i];
-            if (per_op == 4 && op.kind == WS_OP_GEMM) {
+            const OpDesc &op = op_at(i);
+            const bool pre_a = dexec && (*dexec)[i].pre_a, pre_b = dexec && (*dexec)[i].pre_b;
+            g_trace.unsplit_operands += (pre_a ? 1 : 0) + (pre_b ? 1 : 0);
+            if (dexec && op.kind == WS_OP_ADD && exec_uses_digits((*dexec)[i]))
+                g_trace.digit_adds += 1;
+            if (per_op == 4 && op.kind == WS_OP_GEMM && !(pre_a && pre_b)) {
                 float sms = 0.f;
                 if (hipEventElapsedTime(&sms, ev[4 * i + 2], ev[4 * i + 3]) == hipSuccess) {
                     const double M = (double)op.a.rows, K = (double)op.a.cols, N = (double)op.b.cols;
                     const double Mp = std::ceil(M / 128) * 128, Np = std::ceil(N / 128) * 128,
                                  Kp = std::ceil(std::max(K, 1.0) / 64) * 64;
-                    g_trace.split_launches += 2;
+                    g_trace.split_launches += (pre_a ? 0 : 1) + (pre_b ? 0 : 1);
                     g_trace.split_ms += sms;
-                    g_trace.split_bytes += 8.0 * (M * K + K * N) + 3.0 * (Mp + Np) * Kp;
+                    g_trace.split_bytes += (pre_a ? 0.0 : 8.0 * M * K + 3.0 * Mp * Kp) +
+                                           (pre_b ? 0.0 : 8.0 * K * N + 3.0 * Np * Kp);
                 }
             }
             if (op.kind == WS_OP_ADD) {
+                // 8 bytes per residue entry, 3 per entry held as digit planes
+                double per_entry = 0.0;
+                for (int k = 0; k < op.nin; ++k)
+                    per_entry += dexec && (*dexec)[i].in_enc[k] ? 3.0 : 8.0;
+                for (int o = 0; o < op.nout; ++o)
+                    per_entry += dexec && (*dexec)[i].out_enc[o] ? 3.0 : 8.0;
                 g_trace.add_launches += 1;
                 g_trace.add_ms += ms;
-                g_trace.add_bytes += 8.0 * (double)(op.nin + op.nout) * (double)op.out[0].rows *
-                                     (double)op.out[0].cols;
+                g_trace.add_bytes += per_entry * (double)op.out[0].rows * (double)op.out[0].cols;
             } else {
                 g_trace.gemm_launches += 1;
                 g_trace.gemm_ms += ms;
@@ -693,9 +718,24 @@ int wsmul_plan_export(const ws_args *args, ws_op_desc *ops, int64_t cap, int64_t
         return WS_OK;
     try {
         auto plan = get_plan(key);
-        *count = (int64_t)plan->ops.size();
-        for (int64_t i = 0; i < cap && i < *count; ++i)
-            ops[i] = plan->ops[i];
+        if (a.base == WS_BASE_I8_LIMBS && plan->ws_elems > 0) {
+            auto ex = digit_exec(*plan);
+            *count = (int64_t)ex->size();
+            for (int64_t i = 0; i < cap && i < *count; ++i) {
+                const ExecOp &e = (*ex)[i];
+                ops[i] = e.op;
+                for (int k = 0; k < e.op.nin; ++k)
+                    ops[i].in[k].form = e.in_enc[k];
+                for (int o = 0; o < e.op.nout; ++o)
+                    ops[i].out[o].form = e.out_enc[o];
+                ops[i].a.form = e.pre_a ? WS_FORM_DIGITS_A : WS_FORM_RESIDUES;
+                ops[i].b.form = e.pre_b ? WS_FORM_DIGITS_B : WS_FORM_RESIDUES;
+            }
+        } else {
+            *count = (int64_t)plan->ops.size();
+            for (int64_t i = 0; i < cap && i < *count; ++i)
+                ops[i] = plan->ops[i];
+        }
     } catch (const std::exception &e) {
         return fail(WS_EINVAL, std::string("planner: ") + e.what());
     }

@@ -139,6 +139,113 @@ __global__ __launch_bounds__(256) void split_cols_kernel(const T *X, int64_t ld,
     }
 }
 
+// ---- Addition rows on digit planes.  A temporary that only feeds base
+// products (and the next addition rows) may be kept as the three digit
+// planes the product consumes instead of as residues: the A-role layout of
+// the tiled planes above (R x K, K inner), or the B-role one (a K x N block
+// stored as N x K).  This kernel runs one addition group of at most four
+// inputs and four outputs, each a residue view or digit planes, on 64 x 64
+// tiles: every input tile is read (and decoded) into LDS as residues first,
+// so outputs may overwrite inputs; then every output tile is formed and
+// written (encoded).  Digit tiles of 64 inner indices are one K-step of the
+// tiled layout, so every access is a contiguous 16-byte chunk.
+__device__ __forceinline__ int32_t undigit(int8_t d0, int8_t d1, int8_t d2, int32_t p) {
+    const int32_t c = (int32_t)d0 + 256 * (int32_t)d1 + 65536 * (int32_t)d2;
+    return c < 0 ? c + p : c;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void lin_digits_kernel(LinDigitsParams L) {
+    // nin tiles of 64 x 65 int32 (dynamic: fewer inputs, more workgroups per CU)
+    extern __shared__ int32_t lin_lds[];
+    auto val = reinterpret_cast<int32_t(*)[64][65]>(lin_lds);
+    const int64_t r0 = (int64_t)(blockIdx.x / L.tiles_c) * 64;
+    const int64_t c0 = (int64_t)(blockIdx.x % L.tiles_c) * 64;
+    const int tid = threadIdx.x;
+    const int32_t pi = (int32_t)L.p;
+    // Chunk q (16 bytes) of row `row` of the 64-wide K-step block `kt` of a
+    // plane tiled by 128-row tiles.
+    auto chunk_at = [&](const DigitIO &io, int64_t row, int64_t kt, int q) {
+        const int64_t rt = row / TILE;
+        const int rr = (int)(row % TILE);
+        return ((rt * (io.ld / KSTEP) + kt) * (TILE * KSTEP)) + rr * KSTEP + 16 * q;
+    };
+    for (int i = 0; i < L.nin; ++i) {
+        const DigitIO &io = L.in[i];
+        if (io.kind == 0) {
+            const T *X = static_cast<const T *>(io.ptr);
+            const int cc = tid & 63;
+#pragma unroll 4
+            for (int j = 0; j < 16; ++j) {
+                const int rr = (tid >> 6) + 4 * j;
+                val[i][rr][cc] = (int32_t)to_f64(X[(r0 + rr) * io.ld + c0 + cc]);
+            }
+        } else {
+            // A-role: row r0+a of the plane, inner block c0/64.  B-role: row
+            // c0+a of the (transposed) plane, inner block r0/64.
+            const int a = tid >> 2, q = tid & 3;
+            const bool arole = io.kind == 1;
+            const int64_t row = arole ? r0 + a : c0 + a;
+            const int64_t off = chunk_at(io, row, (arole ? c0 : r0) / KSTEP, q);
+            const int8_t *b = static_cast<const int8_t *>(io.ptr) + off;
+            union {
+                uint4 u;
+                int8_t d[16];
+            } x0, x1, x2;
+            x0.u = *reinterpret_cast<const uint4 *>(b);
+            x1.u = *reinterpret_cast<const uint4 *>(b + io.plane);
+            x2.u = *reinterpret_cast<const uint4 *>(b + 2 * io.plane);
+            const int lc = q ^ (((int)(row % TILE) >> 2) & 3);     // logical chunk
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int32_t v = undigit(x0.d[e], x1.d[e], x2.d[e], pi);
+                if (arole)
+                    val[i][a][16 * lc + e] = v;
+                else
+                    val[i][16 * lc + e][a] = v;
+            }
+        }
+    }
+    __syncthreads();
+    for (int o = 0; o < L.nout; ++o) {
+        const DigitIO &io = L.out[o];
+        if (io.kind == 0) {
+            T *Y = static_cast<T *>(const_cast<void *>(io.ptr));
+            const int cc = tid & 63;
+#pragma unroll 4
+            for (int j = 0; j < 16; ++j) {
+                const int rr = (tid >> 6) + 4 * j;
+                double sum = 0.0;
+                for (int i = 0; i < L.nin; ++i)
+                    sum = fma(L.coef[o][i], (double)val[i][rr][cc], sum);
+                Y[(r0 + rr) * io.ld + c0 + cc] = from_f64<T>(mod_reduce(sum, L.p, L.pinv));
+            }
+        } else {
+            const int a = tid >> 2, q = tid & 3;
+            const bool arole = io.kind == 1;
+            const int64_t row = arole ? r0 + a : c0 + a;
+            const int64_t off = chunk_at(io, row, (arole ? c0 : r0) / KSTEP, q);
+            const int lc = q ^ (((int)(row % TILE) >> 2) & 3);
+            union {
+                uint4 u;
+                int8_t d[16];
+            } y0, y1, y2;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                double sum = 0.0;
+                for (int i = 0; i < L.nin; ++i)
+                    sum = fma(L.coef[o][i],
+                              (double)(arole ? val[i][a][16 * lc + e] : val[i][16 * lc + e][a]), sum);
+                digits3(mod_reduce(sum, L.p, L.pinv), L.p, L.half, y0.d[e], y1.d[e], y2.d[e]);
+            }
+            int8_t *b = static_cast<int8_t *>(const_cast<void *>(io.ptr)) + off;
+            *reinterpret_cast<uint4 *>(b) = y0.u;
+            *reinterpret_cast<uint4 *>(b + io.plane) = y1.u;
+            *reinterpret_cast<uint4 *>(b + 2 * io.plane) = y2.u;
+        }
+    }
+}
+
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 struct DigitParams {
@@ -314,8 +421,24 @@ size_t digit_scratch_bytes(int64_t M, int64_t N, int64_t K) {
     return (size_t)(3 * (round_up(M, TILE) + round_up(N, TILE)) * Kp);
 }
 
+hipError_t launch_lin_digits(const LinDigitsParams &L, int dtype, hipStream_t stream) {
+    if (L.R <= 0 || L.Cc <= 0)
+        return hipSuccess;
+    if (L.R % 64 || L.Cc % 64 || L.nin < 1 || L.nin > LD_MAX || L.nout < 1 || L.nout > LD_MAX)
+        return hipErrorInvalidValue;
+    LinDigitsParams P = L;
+    P.tiles_c = (int32_t)(L.Cc / 64);
+    const dim3 grid((uint32_t)((L.R / 64) * (L.Cc / 64)));
+    const uint32_t lds = (uint32_t)(L.nin * 64 * 65 * sizeof(int32_t));
+    if (dtype == WS_I64)
+        ws_launch(lin_digits_kernel<int64_t>, grid, dim3(256), lds, stream, P);
+    else
+        ws_launch(lin_digits_kernel<double>, grid, dim3(256), lds, stream, P);
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtype, int64_t p,
-                             hipStream_t stream) {
+                             hipStream_t stream, bool pre_a, bool pre_b) {
     const int64_t M = op.a.rows, K = op.a.cols, N = op.b.cols;
     if (M == 0 || N == 0)
         return hipSuccess;
@@ -348,8 +471,16 @@ hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtyp
     D.Mp = round_up(M, TILE);
     D.Np = round_up(N, TILE);
     D.Kp = round_up(std::max<int64_t>(K, 1), KSTEP);
+    // Operands already held as digit planes at their views (pre_a, pre_b:
+    // whole tiles, so the padded sizes are the sizes) are read in place.
+    if ((pre_a && (M % TILE || K % KSTEP)) || (pre_b && (N % TILE || K % KSTEP)))
+        return hipErrorInvalidValue;
     int8_t *Ad = static_cast<int8_t *>(bufs.scratch);
     int8_t *Bd = Ad + 3 * D.Mp * D.Kp;
+    if (pre_a)
+        Ad = static_cast<int8_t *>(bufs.ptr[op.a.buf]) + op.a.off * esz;
+    if (pre_b)
+        Bd = static_cast<int8_t *>(bufs.ptr[op.b.buf]) + op.b.off * esz;
     D.Ad = Ad;
     D.Bd = Bd;
     D.c24 = (double)((int64_t(1) << 24) % p);
@@ -363,19 +494,23 @@ hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtyp
         launch_timing() = LaunchTiming{timing.split_start, timing.split_stop, false, nullptr, nullptr};
     const int vec2 = (op.a.ld % 2 == 0 && reinterpret_cast<uintptr_t>(Aop) % 16 == 0) ? 1 : 0;
     if (dtype == WS_I64) {
-        ws_launch(split_rows_kernel<int64_t>, dim3(blocks_a), dim3(256), 0, stream,
-                  static_cast<const int64_t *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
-                  P.p, P.half, vec2);
-        ws_launch(split_cols_kernel<int64_t>, grid_b, dim3(256), 0, stream,
-                  static_cast<const int64_t *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
-                  P.p, P.half);
+        if (!pre_a)
+            ws_launch(split_rows_kernel<int64_t>, dim3(blocks_a), dim3(256), 0, stream,
+                      static_cast<const int64_t *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
+                      P.p, P.half, vec2);
+        if (!pre_b)
+            ws_launch(split_cols_kernel<int64_t>, grid_b, dim3(256), 0, stream,
+                      static_cast<const int64_t *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
+                      P.p, P.half);
     } else {
-        ws_launch(split_rows_kernel<double>, dim3(blocks_a), dim3(256), 0, stream,
-                  static_cast<const double *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
-                  P.p, P.half, vec2);
-        ws_launch(split_cols_kernel<double>, grid_b, dim3(256), 0, stream,
-                  static_cast<const double *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
-                  P.p, P.half);
+        if (!pre_a)
+            ws_launch(split_rows_kernel<double>, dim3(blocks_a), dim3(256), 0, stream,
+                      static_cast<const double *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
+                      P.p, P.half, vec2);
+        if (!pre_b)
+            ws_launch(split_cols_kernel<double>, grid_b, dim3(256), 0, stream,
+                      static_cast<const double *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
+                      P.p, P.half);
     }
     launch_timing() = timing;
     hipError_t e = hipGetLastError();

@@ -83,6 +83,12 @@ bool disjoint(const View &a, const View &b) {
     return a1 <= b0 || b1 <= a0;
 }
 
+}  // namespace
+
+bool views_disjoint(const View &a, const View &b) { return disjoint(a, b); }
+
+namespace {
+
 struct Term {
     int64_t c;
     View v;

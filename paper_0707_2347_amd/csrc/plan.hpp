@@ -10,6 +10,8 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -55,6 +57,10 @@ struct Plan {
     int64_t element_additions = 0;
     int64_t base_flops = 0;
     int64_t add_ops = 0, gemm_ops = 0;
+    // Per-base execution lists derived from ops on first use (the digit
+    // base's temporaries held as digit planes), kept with the plan.
+    mutable std::mutex exec_mu;
+    mutable std::shared_ptr<const void> exec_cache;
 };
 
 // Validation result for a (schedule, shape, beta) request.
@@ -69,6 +75,10 @@ struct Resolved {
 // `blocks` is t of the blocked schedules (ignored by the others).
 Resolved resolve_schedule(int schedule, int64_t m, int64_t k, int64_t n, bool beta_nonzero,
                           int levels, int blocks = 2);
+
+// Do two views share no element?  Exact for views of one leading dimension,
+// by the address spans they touch otherwise.
+bool views_disjoint(const View &a, const View &b);
 
 // Build the plan for an already resolved request.
 void build_plan(const PlanKey &key, Plan &plan);

@@ -5,6 +5,7 @@
 
 #include <memory>
 #include <string>
+#include <vector>
 
 #include "kernels.hpp"
 #include "plan.hpp"
@@ -32,7 +33,42 @@ int autotune_choice(ws_args &a, bool beta_nonzero);
 // Base products from signed 8-bit digits of centred residues.
 bool limbs_supported(int64_t p);
 size_t digit_scratch_bytes(int64_t M, int64_t N, int64_t K);
+// pre_a / pre_b: that operand's view already holds its digit planes
+// (A-role or B-role layout of whole tiles), so it is not split.
 hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtype, int64_t p,
-                             hipStream_t stream);
+                             hipStream_t stream, bool pre_a = false, bool pre_b = false);
+
+// One addition group on residue views and digit planes (see limbs.hip).
+constexpr int LD_MAX = 4;
+struct DigitIO {
+    int32_t kind;          // 0 residues (storage type), 1 A-role planes, 2 B-role planes
+    int32_t pad;
+    const void *ptr;       // element (0, 0) of the view, or plane 0 of the digits
+    int64_t ld;            // residues: leading dimension; digits: inner length of the planes
+    int64_t plane;         // digits: bytes per plane
+};
+struct LinDigitsParams {
+    DigitIO in[LD_MAX], out[LD_MAX];
+    int32_t nin, nout, tiles_c, pad;
+    int64_t R, Cc;         // rows and columns of the group's views (multiples of 64)
+    double p, pinv, half;
+    double coef[LD_MAX][LD_MAX];
+};
+hipError_t launch_lin_digits(const LinDigitsParams &L, int dtype, hipStream_t stream);
+
+// An operation of a plan as the digit base runs it: which inputs and
+// outputs of an addition group are digit planes (0 residues, 1 A-role,
+// 2 B-role) and which operands of a base product already are.
+struct ExecOp {
+    OpDesc op;
+    int8_t in_enc[WS_MAX_IN];
+    int8_t out_enc[WS_MAX_OUT];
+    bool pre_a, pre_b;
+};
+// The digit base's execution list of a plan (digit_temps.cpp), built once.
+std::shared_ptr<const std::vector<ExecOp>> digit_exec(const Plan &plan);
+bool exec_uses_digits(const ExecOp &e);
+hipError_t launch_exec_add(const ExecOp &e, const DevBufs &bufs, int dtype, int64_t p,
+                           hipStream_t stream);
 
 }  // namespace wsmul

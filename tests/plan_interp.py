@@ -28,20 +28,81 @@ def _modprod(X, Y, p):
     return s
 
 
+POISON = -(1 << 40)    # stands for bytes that hold digit planes: never a residue
+
+
+def _span(v):
+    return v.off, v.off + (v.rows - 1) * v.ld + v.cols
+
+
+def _meets(v, w):
+    if v.buf != w.buf or 0 in (v.rows, v.cols, w.rows, w.cols):
+        return False
+    a0, a1 = _span(v)
+    b0, b1 = _span(w)
+    return a0 < b1 and b0 < a1
+
+
+def _key(v):
+    return (v.buf, v.off, v.rows, v.cols, v.ld)
+
+
+def _check_planes_view(v, form):
+    """The layout conditions the device needs for a view held as digit planes."""
+    assert v.buf == capi.WS_BUF_W and v.ld == v.cols and v.off % 2 == 0, "planes view not dense"
+    if form == capi.WS_FORM_DIGITS_A:
+        assert v.rows % 128 == 0 and v.cols % 64 == 0, "A-role planes need whole tiles"
+    else:
+        assert form == capi.WS_FORM_DIGITS_B, "unknown form"
+        assert v.cols % 128 == 0 and v.rows % 64 == 0, "B-role planes need whole tiles"
+
+
 def run(ops, bufs, p):
-    """bufs: [A, B, C, W] flat int64 arrays, modified in place."""
+    """bufs: [A, B, C, W] flat int64 arrays, modified in place.
+
+    Views whose form is a digit-plane form (the digit base's execution list)
+    are kept aside, keyed by view and form, while their block is overwritten
+    with a value that is no residue: a read of such a block as residues, a
+    read of planes nobody wrote, or a group that reads a view in one form and
+    writes it in another (on the device its workgroups would overwrite bytes
+    others still read) fails."""
+    planes = {}
+
+    def read(v):
+        if v.form:
+            _check_planes_view(v, v.form)
+            assert (_key(v), v.form) in planes, "digit planes read before they were written"
+            return planes[(_key(v), v.form)].copy()
+        x = _view(bufs[v.buf], v).copy()
+        assert not np.any(x == POISON), "residues read from a block that holds digit planes"
+        return x
+
+    def write(v, x):
+        for k in [k for k in planes if _meets(v, _Viewish(k[0]))]:
+            del planes[k]
+        if v.form:
+            _check_planes_view(v, v.form)
+            planes[(_key(v), v.form)] = x
+            _view(bufs[v.buf], v)[...] = POISON
+        else:
+            _view(bufs[v.buf], v)[...] = x
+
     for op in ops:
         nin, nout = op.nin, op.nout
         ins = [None] * nin
         if op.kind == capi.WS_OP_GEMM:
-            a = _view(bufs[op.a.buf], op.a)
-            b = _view(bufs[op.b.buf], op.b)
+            a = read(op.a)
+            b = read(op.b)
             ins[0] = (op.alpha % p) * _modprod(a, b, p) % p
             first = 1
         else:
             first = 0
+            for i in range(nin):
+                for o in range(nout):
+                    if _key(op.in_[i]) == _key(op.out[o]):
+                        assert op.in_[i].form == op.out[o].form, "view rewritten in another form"
         for i in range(first, nin):
-            ins[i] = _view(bufs[op.in_[i].buf], op.in_[i]).copy()
+            ins[i] = read(op.in_[i])
         outs = []
         for o in range(nout):
             acc = np.zeros_like(ins[0] if ins[0] is not None else ins[first])
@@ -49,4 +110,11 @@ def run(ops, bufs, p):
                 acc = (acc + int(op.coef[o][i]) * ins[i]) % p
             outs.append(acc)
         for o in range(nout):
-            _view(bufs[op.out[o].buf], op.out[o])[...] = outs[o]
+            write(op.out[o], outs[o])
+
+
+class _Viewish:
+    """A view rebuilt from a planes key (for the overlap test)."""
+
+    def __init__(self, key):
+        self.buf, self.off, self.rows, self.cols, self.ld = key

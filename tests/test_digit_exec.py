@@ -1,0 +1,126 @@
+"""Host-side checks of the digit base's execution list (no GPU).
+
+On the 8-bit digit base the library runs a plan's operations with some
+workspace temporaries held as digit planes instead of residues (their view's
+form, include/wsmul.h).  wsmul_plan_export returns that list for the digit
+base; the numpy stand-in (tests/plan_interp.py) runs it with every
+digit-plane block overwritten by a non-residue while the values are kept
+aside, so a residue read of such a block, a planes read of a block nobody
+encoded, a group rewriting a view in another form, or a planes view the
+device could not lay out fails.  The result must equal the oracle and the
+final inputs the oracle's replay.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ref
+from oracle.schedules import replay
+from paper_0707_2347_amd import capi, inputs
+
+from . import plan_interp
+
+pytestmark = pytest.mark.skipif(not os.path.exists(capi.LIB_PATH),
+                                reason="libwsmul.so not built")
+I8 = capi.WS_BASE_I8_LIMBS
+
+REPLAY = {
+    (capi.WS_TWO_TEMP, False): "t1", (capi.WS_TWO_TEMP, True): "acc",
+    (capi.WS_OVERWRITE, False): "ip", (capi.WS_OVERWRITE, True): "aclr",
+    (capi.WS_HL_THREE_TEMP, True): "hl", (capi.WS_HL_THREE_TEMP, False): "hl",
+    (capi.WS_ACCR, True): "accr", (capi.WS_ACR, True): "acr",
+    (capi.WS_READONLY_INPLACE, False): "ipmm",
+}
+
+
+def _export(schedule, m, k, n, p, alpha, beta, levels, base=I8, flags=0):
+    args = capi.make_args(m, k, n, p, alpha=alpha, beta=beta, schedule=schedule,
+                          levels=levels, base=base, flags=flags)
+    return capi.wsmul_plan_info(args), capi.wsmul_plan_export(args)
+
+
+def _forms(ops):
+    views = []
+    for op in ops:
+        views += [op.in_[i] for i in range(op.nin)] + [op.out[o] for o in range(op.nout)]
+        if op.kind == capi.WS_OP_GEMM:
+            views += [op.a, op.b]
+    return sum(1 for v in views if v.form)
+
+
+CASES = [
+    # schedule, (m, k, n), levels, accumulate, digit forms expected
+    (capi.WS_TWO_TEMP, (256, 256, 256), 1, False, True),
+    (capi.WS_TWO_TEMP, (512, 512, 512), 2, False, True),
+    (capi.WS_TWO_TEMP, (1024, 1024, 1024), 3, False, True),
+    (capi.WS_TWO_TEMP, (512, 256, 384), 1, False, True),
+    (capi.WS_TWO_TEMP, (384, 512, 256), 1, False, True),
+    (capi.WS_TWO_TEMP, (320, 320, 320), 1, False, False),     # 160-row blocks: no whole tiles
+    (capi.WS_TWO_TEMP, (512, 512, 512), 2, True, True),
+    (capi.WS_TWO_TEMP, (256, 256, 256), 1, True, True),
+    (capi.WS_HL_THREE_TEMP, (512, 512, 512), 1, True, True),
+    (capi.WS_HL_THREE_TEMP, (512, 512, 512), 2, True, True),
+    (capi.WS_HL_THREE_TEMP, (512, 384, 256), 1, True, True),
+    (capi.WS_HL_THREE_TEMP, (512, 512, 512), 1, False, True),
+    (capi.WS_OVERWRITE, (512, 512, 512), 1, True, True),
+    (capi.WS_OVERWRITE, (512, 512, 512), 2, True, True),
+    (capi.WS_OVERWRITE, (512, 512, 512), 2, False, False),    # Table 3: no temporaries
+    (capi.WS_ACCR, (512, 512, 512), 1, True, True),
+    (capi.WS_ACR, (512, 512, 512), 1, True, True),
+    (capi.WS_ACR, (512, 256, 768), 1, True, True),
+    (capi.WS_READONLY_INPLACE, (512, 512, 512), 1, False, False),
+]
+
+
+@pytest.mark.parametrize("fuse", [True, False])
+@pytest.mark.parametrize("schedule,shape,levels,acc,digits", CASES)
+def test_execution_list_reproduces_oracle(schedule, shape, levels, acc, digits, fuse):
+    m, k, n = shape
+    p = 1048573 if levels % 2 else 16711421
+    alpha, beta = (3, p - 5) if acc else (p - 1, 0)
+    seed = m + 3 * k + 7 * n + levels
+    A, B, C = inputs.uniform(seed, m, k, n, p, with_c=True)
+    info, ops = _export(schedule, m, k, n, p, alpha, beta, levels,
+                        flags=0 if fuse else capi.WS_FLAG_NOFUSE)
+    assert (_forms(ops) > 0) == digits
+    rng = np.random.default_rng(seed)
+    W = rng.integers(0, p, size=max(info.workspace_bytes // 8, 1))
+    Cg = C.copy() if beta else rng.integers(0, p, size=(m, n))
+    bufs = [A.copy().ravel(), B.copy().ravel(), Cg.ravel().copy(), W]
+    plan_interp.run(ops, bufs, p)
+    assert np.array_equal(bufs[2].reshape(m, n), ref.matmul_mod_p(A, B, C, alpha, beta, p))
+    r = replay(REPLAY[(schedule, acc)], A, B, C, alpha, beta, p, levels)
+    assert np.array_equal(bufs[0].reshape(m, k), r.A) and np.array_equal(bufs[1].reshape(k, n), r.B)
+
+
+def test_table1_execution_list():
+    """Table 1, one level: every temporary is held as digit planes.  S and T
+    blocks are written as planes by the pre-additions (T4 by a group moved
+    out of P1's epilogue), P5, P6 and P7 read both operands as planes, P3 its
+    A operand and P4 its B operand; P1 and P2 read inputs."""
+    info, ops = _export(capi.WS_TWO_TEMP, 512, 512, 512, 65521, 1, 0, 1)
+    _, plain = _export(capi.WS_TWO_TEMP, 512, 512, 512, 65521, 1, 0, 1,
+                       base=capi.WS_BASE_F64_MFMA)
+    assert len(ops) == len(plain) + 1 == 12
+    gemms = [op for op in ops if op.kind == capi.WS_OP_GEMM]
+    assert [(g.a.form, g.b.form) for g in gemms] == [(1, 2), (1, 2), (1, 2), (1, 0), (0, 0),
+                                                   (0, 2), (0, 0)]
+    adds = [op for op in ops if op.kind == capi.WS_OP_ADD]
+    assert len(adds) == 5
+    for op in adds:
+        assert all(op.out[o].form for o in range(op.nout))
+    assert _forms(plain) == 0
+
+
+def test_misplaced_planes_are_caught():
+    """The stand-in fails when a block holding planes is read as residues
+    (the check the tests above rely on): flip one consumer to residues."""
+    _, ops = _export(capi.WS_TWO_TEMP, 256, 256, 256, 65521, 1, 0, 1)
+    g = next(op for op in ops if op.kind == capi.WS_OP_GEMM and op.a.form)
+    g.a.form = 0
+    A, B, _ = inputs.uniform(1, 256, 256, 256, 65521, with_c=True)
+    bufs = [A.ravel().copy(), B.ravel().copy(), np.zeros(256 * 256, np.int64),
+            np.zeros(2 * 128 * 128, np.int64)]
+    with pytest.raises(AssertionError, match="holds digit planes"):
+        plan_interp.run(ops, bufs, 65521)
