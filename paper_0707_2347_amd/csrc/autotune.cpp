@@ -7,16 +7,18 @@
 //     whole 128 x 128 tiles, 58 (50) for ragged large products, 45 / 30
 //     TFLOP/s for the 64 x 64 class with whole / ragged tiles, 25 / 19 for
 //     the small class, 7 us floor per launch;
-//   base products, 8-bit digits: 305 / 295 / 255 / 210 / 45 TFLOP/s
-//     (equivalent) by 128 x 128 tile count (16384^3, 8192^3, 4096^3, 2048^3,
-//     1024^3 measured, the product's store included; other epilogue streams
-//     at 10 TB/s, as they mostly overlap other tiles' products), plus the
+//   base products, 8-bit digits: 310 / 255 / 210 / 45 TFLOP/s (equivalent)
+//     by 128 x 128 tile count (8192^3 and 16384^3, 4096^3, 2048^3, 1024^3
+//     measured, the product's store included; every other epilogue stream
+//     at 3.2 TB/s, measured per product inside Tables 1 and 2), plus the
 //     digit split passes of operands that are not already digit planes
 //     (bytes at 5.5 TB/s);
 //   addition groups: bytes moved at 4.5 TB/s (5.0 TB/s for the digit base's
 //     groups on digit-plane temporaries, 3 bytes per such entry), 4 us floor
 //     per launch.
-// The cheapest candidate whose temporaries fit the memory budget wins.
+// The cheapest candidate whose temporaries fit the memory budget wins; a
+// candidate with temporaries is charged 1% extra (the model's error), so that
+// within it the schedule without extra memory is kept.
 // Overwriting schedules are never chosen automatically (they destroy A, B).
 // For accumulating products the blocked accumulation of Section 7.2 (t = 2,
 // 3, 4 over Table 2, or over Table 9 when square) is a candidate too: it is
@@ -57,8 +59,7 @@ double gemm_f64_us(int64_t M, int64_t N, int64_t K, int64_t p) {
 double gemm_digits_us(int64_t M, int64_t N, int64_t K, bool pre_a = false, bool pre_b = false) {
     const double flops = 2.0 * (double)M * (double)N * (double)K;
     const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
-    const double rate = tiles >= 8192   ? 305e12
-                        : tiles >= 2048 ? 295e12
+    const double rate = tiles >= 2048   ? 310e12
                         : tiles >= 512  ? 255e12
                         : tiles >= 128  ? 210e12
                                         : 45e12;
@@ -234,7 +235,10 @@ bool search(const Key &key, Choice &best, Resolved *reject) {
             if ((size_t)plan->ws_elems * 8u > key.budget)
                 continue;
             for (int base : bases) {
-                const double c = plan_cost_us(*plan, base);
+                // A plan with temporaries must win by more than the cost
+                // model's error (about 1%) over one without: within that,
+                // less memory decides.
+                const double c = plan_cost_us(*plan, base) * (plan->ws_elems > 0 ? 1.01 : 1.0);
                 if (c < best.cost_us) {
                     best = Choice{sched, l, base, blocked ? t : key.blocks, c};
                     found = true;
@@ -256,10 +260,11 @@ double plan_cost_us(const Plan &plan, int base) {
             const OpDesc &op = e.op;
             const double elems = (double)op.out[0].rows * (double)op.out[0].cols;
             if (op.kind == WS_OP_GEMM) {
-                // the rates include the product's own store; further epilogue
-                // streams mostly overlap other tiles' products (~10 TB/s)
+                // the rates include the product's own store; every further
+                // epilogue stream adds its bytes at ~3.2 TB/s (all tiles of a
+                // round run their epilogues together, after their products)
                 t += gemm_digits_us(op.a.rows, op.b.cols, op.a.cols, e.pre_a, e.pre_b);
-                t += 8.0 * (double)(op.nin - 1 + op.nout - 1) * elems / 10e12 * 1e6;
+                t += 8.0 * (double)(op.nin - 1 + op.nout - 1) * elems / 3.2e12 * 1e6;
             } else {
                 double per = 0.0;
                 for (int i = 0; i < op.nin; ++i)
