@@ -74,7 +74,7 @@ def log(msg):
 def kernels_digest():
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels.hip", "limbs.hip", "gemm_common.hpp", "device.hpp"):
+    for name in ("kernels.hip", "limbs.hip", "gemm_common.hpp", "device.hpp", "digit_temps.cpp"):
         with open(os.path.join(ROOT, "paper_0707_2347_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

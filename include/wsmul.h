@@ -401,9 +401,11 @@ typedef struct ws_view {
  * whole tiles (A role: rows % 128 == 0, cols % 64 == 0; B role:
  * cols % 128 == 0, rows % 64 == 0) and is never read as residues before
  * something rewrites it.  The forms appear in wsmul_plan_export's output
- * for the digit base (the execution list it runs); epilogue rows that do
- * not read the product may be moved there into an addition group of their
- * own just before it. */
+ * for the digit base (the execution list it runs).  In that list, epilogue
+ * rows that do not read the product may move into an addition group of their
+ * own just before it, and a product with four or more epilogue streams
+ * besides its own store keeps only an output that is the product itself,
+ * its other rows moving into an addition group right after it. */
 enum { WS_FORM_RESIDUES = 0, WS_FORM_DIGITS_A = 1, WS_FORM_DIGITS_B = 2 };
 
 /* out[o] <- sum_i coef[o][i] * in[i]  (mod p), elementwise.  For a base

@@ -13,7 +13,8 @@
 // An epilogue row that does not read the product (Table 1 forms T4 in the
 // epilogue of P1) is moved into an addition group of its own just before
 // the product, so that the temporary it reads and the one it writes qualify
-// too.  The analysis runs once per plan and is kept with it.
+// too; heavy epilogues move into a group after the product.  The analysis
+// runs once per plan and is kept with it.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -135,6 +136,65 @@ void extract_epilogue_rows(std::vector<ExecOp> &ops) {
     ops.swap(out);
 }
 
+// A digit product runs its epilogue after its matrix-core work, every tile
+// of a round at once, so each epilogue stream beyond the product's own store
+// costs its bytes at about 3.2 TB/s, where an addition group moves them at
+// about 5 TB/s.  A product with HEAVY_EPILOGUE or more such streams keeps
+// only an output that is the product itself, and the other rows move to an
+// addition group right after it that reads that output back.
+constexpr int HEAVY_EPILOGUE = 4;
+
+void split_heavy_epilogues(std::vector<ExecOp> &ops) {
+    std::vector<ExecOp> out;
+    out.reserve(ops.size() + 8);
+    for (const ExecOp &e : ops) {
+        const OpDesc &g = e.op;
+        if (g.kind != WS_OP_GEMM || (g.nin - 1) + (g.nout - 1) < HEAVY_EPILOGUE) {
+            out.push_back(e);
+            continue;
+        }
+        int star = -1;
+        for (int o = 0; o < g.nout && star < 0; ++o) {
+            bool ok = g.coef[o][0] == 1;
+            for (int i = 1; ok && i < g.nin; ++i)
+                ok = g.coef[o][i] == 0 && !overlap(g.out[o], g.in[i]);
+            for (int o2 = 0; ok && o2 < g.nout; ++o2)
+                ok = o2 == o || !overlap(g.out[o], g.out[o2]);
+            ok = ok && !overlap(g.out[o], g.a) && !overlap(g.out[o], g.b);
+            if (ok)
+                star = o;
+        }
+        if (star < 0) {
+            out.push_back(e);
+            continue;
+        }
+        ExecOp prod = e;
+        prod.op.nin = 1;
+        prod.op.nout = 1;
+        prod.op.out[0] = g.out[star];
+        std::memset(prod.op.coef, 0, sizeof(prod.op.coef));
+        prod.op.coef[0][0] = 1;
+        ExecOp add{};
+        add.op.kind = WS_OP_ADD;
+        add.op.depth = g.depth;
+        add.op.nin = g.nin;
+        add.op.in[0] = g.out[star];          // the product, read back
+        for (int i = 1; i < g.nin; ++i)
+            add.op.in[i] = g.in[i];
+        for (int o = 0; o < g.nout; ++o) {
+            if (o == star)
+                continue;
+            add.op.out[add.op.nout] = g.out[o];
+            for (int i = 0; i < g.nin; ++i)
+                add.op.coef[add.op.nout][i] = g.coef[o][i];
+            ++add.op.nout;
+        }
+        out.push_back(prod);
+        out.push_back(add);
+    }
+    ops.swap(out);
+}
+
 // Producer (op, output) pairs barred from holding digits.
 using Banned = std::vector<std::pair<size_t, int>>;
 
@@ -249,6 +309,7 @@ std::shared_ptr<const std::vector<ExecOp>> digit_exec(const Plan &plan) {
         ops->push_back(e);
     }
     extract_epilogue_rows(*ops);
+    split_heavy_epilogues(*ops);
     assign_encodings(*ops);
     plan.exec_cache = ops;
     return ops;
