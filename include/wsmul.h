@@ -401,7 +401,11 @@ typedef struct ws_view {
  * whole tiles (A role: rows % 128 == 0, cols % 64 == 0; B role:
  * cols % 128 == 0, rows % 64 == 0) and is never read as residues before
  * something rewrites it.  The forms appear in wsmul_plan_export's output
- * for the digit base (the execution list it runs).  In that list, epilogue
+ * for the digit base (the execution list it runs).  Views of A and B may
+ * carry a form too when the plan never writes that input: the call then
+ * splits the whole input into digit planes once, in its digit scratch, and
+ * such views (whole tiles of those planes) are read from there.  In that
+ * list, epilogue
  * rows that do not read the product may move into an addition group of their
  * own just before it, and a product with four or more epilogue streams
  * besides its own store keeps only an output that is the product itself,

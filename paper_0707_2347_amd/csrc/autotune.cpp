@@ -7,9 +7,10 @@
 //     whole 128 x 128 tiles, 58 (50) for ragged large products, 45 / 30
 //     TFLOP/s for the 64 x 64 class with whole / ragged tiles, 25 / 19 for
 //     the small class, 7 us floor per launch;
-//   base products, 8-bit digits: 310 / 255 / 210 / 45 TFLOP/s (equivalent)
-//     by 128 x 128 tile count (8192^3 and 16384^3, 4096^3, 2048^3, 1024^3
-//     measured, the product's store included; every other epilogue stream
+//   base products, 8-bit digits: 318 / 310 / 255 / 210 / 45 TFLOP/s
+//     (equivalent) by 128 x 128 tile count (16384^3, 8192^3 and 12288^3,
+//     4096^3, 2048^3, 1024^3 measured, the product's store included; every
+//     other epilogue stream
 //     at 3.2 TB/s, measured per product inside Tables 1 and 2), plus the
 //     digit split passes of operands that are not already digit planes
 //     (bytes at 5.5 TB/s);
@@ -59,7 +60,8 @@ double gemm_f64_us(int64_t M, int64_t N, int64_t K, int64_t p) {
 double gemm_digits_us(int64_t M, int64_t N, int64_t K, bool pre_a = false, bool pre_b = false) {
     const double flops = 2.0 * (double)M * (double)N * (double)K;
     const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
-    const double rate = tiles >= 2048   ? 310e12
+    const double rate = tiles >= 16384  ? 318e12
+                        : tiles >= 2048 ? 310e12
                         : tiles >= 512  ? 255e12
                         : tiles >= 128  ? 210e12
                                         : 45e12;
@@ -256,7 +258,11 @@ double plan_cost_us(const Plan &plan, int base) {
     if (base == WS_BASE_I8_LIMBS) {
         // the digit base's execution list: temporaries held as digit planes
         // move 3 bytes per entry and spare their products' splits
-        for (const ExecOp &e : *digit_exec(plan)) {
+        const auto x = digit_exec(plan);
+        // whole inputs split once into planes
+        t += (x->split_a ? 5.0 + 11.0 * (double)plan.key.m * (double)plan.key.k / 5.5e12 * 1e6 : 0.0) +
+             (x->split_b ? 5.0 + 11.0 * (double)plan.key.k * (double)plan.key.n / 5.5e12 * 1e6 : 0.0);
+        for (const ExecOp &e : x->ops) {
             const OpDesc &op = e.op;
             const double elems = (double)op.out[0].rows * (double)op.out[0].cols;
             if (op.kind == WS_OP_GEMM) {

@@ -206,29 +206,45 @@ static hipError_t launch_add_rows(const OpDesc &op, const DevBufs &bufs, int dty
     return err;
 }
 
+// The digit base runs a plan's execution list (temporaries that only feed
+// base products and addition groups stay digit planes, inputs may be read
+// from planes of the whole input) when the workspace is 16-byte aligned.
+std::shared_ptr<const DigitExec> exec_list(const Plan &plan, const ws_args &a, const void *ws) {
+    if (a.base != WS_BASE_I8_LIMBS || !ws || reinterpret_cast<uintptr_t>(ws) % 16 != 0)
+        return nullptr;
+    return digit_exec(plan);
+}
+
+// Digit scratch of one call: the input planes and the largest split of a
+// base product (execution list), or the largest base product's splits.
+size_t digit_scratch_need(const Plan &plan, const ws_args &a, const DigitExec *x) {
+    if (a.base != WS_BASE_I8_LIMBS)
+        return 0;
+    if (x)
+        return x->input_bytes + x->split_bytes;
+    size_t bytes = 0;
+    for (const OpDesc &op : plan.ops)
+        if (op.kind == WS_OP_GEMM)
+            bytes = std::max(bytes, digit_scratch_bytes(op.a.rows, op.b.cols, op.a.cols));
+    return bytes;
+}
+
 // Launch every operation of a plan on `stream`.
 int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, bool trace,
-             void *scratch, size_t scratch_bytes) {
+             void *scratch, size_t scratch_bytes, const DigitExec *dexec) {
     DevBufs bufs{{a.A, a.B, a.C, ws}, scratch, scratch_bytes};
+    if (dexec && scratch_bytes < dexec->input_bytes + dexec->split_bytes)
+        return fail(WS_EINVAL, "digit scratch smaller than the execution list needs");
     // Traced runs: a start/stop event pair per operation, stamped by the
     // kernel dispatches themselves.
-    // The digit base gets a second pair per operation for its splits.
+    // The digit base gets a second pair per operation for its splits, and
+    // one more pair for the splits of whole inputs.
     const size_t per_op = a.base == WS_BASE_I8_LIMBS ? 4 : 2;
-    // The digit base runs the plan's execution list, in which temporaries
-    // that only feed base products and addition groups stay digit planes.
-    std::shared_ptr<const std::vector<ExecOp>> dexec;
-    if (a.base == WS_BASE_I8_LIMBS && ws && reinterpret_cast<uintptr_t>(ws) % 16 == 0) {
-        try {
-            dexec = digit_exec(plan);
-        } catch (const std::exception &e) {
-            return fail(WS_ENOMEM, std::string("digit execution list: ") + e.what());
-        }
-    }
-    const size_t nops = dexec ? dexec->size() : plan.ops.size();
-    auto op_at = [&](size_t i) -> const OpDesc & { return dexec ? (*dexec)[i].op : plan.ops[i]; };
+    const size_t nops = dexec ? dexec->ops.size() : plan.ops.size();
+    auto op_at = [&](size_t i) -> const OpDesc & { return dexec ? dexec->ops[i].op : plan.ops[i]; };
     std::vector<hipEvent_t> ev;
     if (trace) {
-        ev.assign(per_op * nops, nullptr);
+        ev.assign(per_op * nops + 2, nullptr);
         for (auto &e : ev)
             if (hipEventCreate(&e) != hipSuccess) {
                 for (auto &d : ev)
@@ -244,6 +260,15 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
     if (const char *f = std::getenv("WSMUL_FAULT_AT"))
         fault_at = std::strtol(f, nullptr, 10);
     int rc = WS_OK;
+    const bool input_splits = dexec && (dexec->split_a || dexec->split_b);
+    if (input_splits) {
+        if (trace)
+            launch_timing() = LaunchTiming{ev[per_op * nops], ev[per_op * nops + 1], false};
+        const hipError_t err = launch_input_splits(*dexec, bufs, a.lda, a.ldb, a.m, a.k, a.n,
+                                                   a.dtype, a.p, stream);
+        if (err != hipSuccess)
+            rc = fail(WS_EHIP, std::string("kernel launch failed: ") + hipGetErrorString(err));
+    }
     for (size_t i = 0; i < nops && rc == WS_OK; ++i) {
         const OpDesc &op = op_at(i);
         if (fault_at >= 0 && (size_t)fault_at == i) {
@@ -256,13 +281,16 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
                                                          ev[4 * i + 2], ev[4 * i + 3]}
                                           : LaunchTiming{ev[2 * i], ev[2 * i + 1], false};
         hipError_t err;
-        if (op.kind == WS_OP_ADD)
-            err = dexec && exec_uses_digits((*dexec)[i])
-                      ? launch_exec_add((*dexec)[i], bufs, a.dtype, a.p, stream)
-                      : launch_add_rows(op, bufs, a.dtype, a.p, stream);
+        if (dexec)
+            err = op.kind == WS_OP_ADD
+                      ? (exec_uses_digits(dexec->ops[i])
+                             ? launch_exec_add(*dexec, dexec->ops[i], bufs, a.dtype, a.p, stream)
+                             : launch_add_rows(op, bufs, a.dtype, a.p, stream))
+                      : launch_exec_gemm(*dexec, dexec->ops[i], bufs, a.dtype, a.p, stream);
+        else if (op.kind == WS_OP_ADD)
+            err = launch_add_rows(op, bufs, a.dtype, a.p, stream);
         else if (a.base == WS_BASE_I8_LIMBS)
-            err = launch_gemm_limbs(op, bufs, a.dtype, a.p, stream, dexec && (*dexec)[i].pre_a,
-                                    dexec && (*dexec)[i].pre_b);
+            err = launch_gemm_limbs(op, bufs, a.dtype, a.p, stream);
         else
             err = launch_gemm(op, bufs, a.dtype, a.p, stream);
         if (err != hipSuccess)
@@ -272,14 +300,24 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
     if (trace) {
         if (rc == WS_OK && hipStreamSynchronize(stream) != hipSuccess)
             rc = fail(WS_EHIP, "hipStreamSynchronize failed");
+        if (rc == WS_OK && input_splits) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[per_op * nops], ev[per_op * nops + 1]) == hipSuccess) {
+                const double Ka = (double)dexec->a_kp, Kb = (double)dexec->b_kp;
+                g_trace.split_launches += (dexec->split_a ? 1 : 0) + (dexec->split_b ? 1 : 0);
+                g_trace.split_ms += ms;
+                g_trace.split_bytes += (dexec->split_a ? 8.0 * a.m * a.k + 3.0 * dexec->a_rows * Ka : 0.0) +
+                                       (dexec->split_b ? 8.0 * a.k * a.n + 3.0 * dexec->b_cols * Kb : 0.0);
+            }
+        }
         for (size_t i = 0; i < nops && rc == WS_OK; ++i) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, ev[per_op * i], ev[per_op * i + 1]) != hipSuccess)
                 ms = 0.f;   // an operation with no kernel (empty view)
             const OpDesc &op = op_at(i);
-            const bool pre_a = dexec && (*dexec)[i].pre_a, pre_b = dexec && (*dexec)[i].pre_b;
+            const bool pre_a = dexec && dexec->ops[i].pre_a, pre_b = dexec && dexec->ops[i].pre_b;
             g_trace.unsplit_operands += (pre_a ? 1 : 0) + (pre_b ? 1 : 0);
-            if (dexec && op.kind == WS_OP_ADD && exec_uses_digits((*dexec)[i]))
+            if (dexec && op.kind == WS_OP_ADD && exec_uses_digits(dexec->ops[i]))
                 g_trace.digit_adds += 1;
             if (per_op == 4 && op.kind == WS_OP_GEMM && !(pre_a && pre_b)) {
                 float sms = 0.f;
@@ -297,9 +335,9 @@ int run_plan(const Plan &plan, const ws_args &a, void *ws, hipStream_t stream, b
                 // 8 bytes per residue entry, 3 per entry held as digit planes
                 double per_entry = 0.0;
                 for (int k = 0; k < op.nin; ++k)
-                    per_entry += dexec && (*dexec)[i].in_enc[k] ? 3.0 : 8.0;
+                    per_entry += dexec && dexec->ops[i].in_enc[k] ? 3.0 : 8.0;
                 for (int o = 0; o < op.nout; ++o)
-                    per_entry += dexec && (*dexec)[i].out_enc[o] ? 3.0 : 8.0;
+                    per_entry += dexec && dexec->ops[i].out_enc[o] ? 3.0 : 8.0;
                 g_trace.add_launches += 1;
                 g_trace.add_ms += ms;
                 g_trace.add_bytes += per_entry * (double)op.out[0].rows * (double)op.out[0].cols;
@@ -357,15 +395,19 @@ int execute(const ws_args &a, const PlanKey &key) {
             return rc;
         }
     }
-    // Digit planes for the INT8 base: sized for the largest base product.
-    size_t scratch_bytes = 0;
+    // Digit planes for the INT8 base.
+    std::shared_ptr<const DigitExec> dexec;
+    try {
+        dexec = exec_list(*plan, a, ws);
+    } catch (const std::exception &e) {
+        release_ws();
+        g_stats.live_alloc_bytes = g_live_bytes.load();
+        return fail(WS_ENOMEM, std::string("digit execution list: ") + e.what());
+    }
+    const size_t scratch_bytes = digit_scratch_need(*plan, a, dexec.get());
     void *scratch = nullptr;
-    if (a.base == WS_BASE_I8_LIMBS) {
-        for (const OpDesc &op : plan->ops)
-            if (op.kind == WS_OP_GEMM)
-                scratch_bytes = std::max(scratch_bytes,
-                                         digit_scratch_bytes(op.a.rows, op.b.cols, op.a.cols));
-        if (scratch_bytes && hipMallocAsync(&scratch, scratch_bytes, stream) != hipSuccess) {
+    if (scratch_bytes) {
+        if (hipMallocAsync(&scratch, scratch_bytes, stream) != hipSuccess) {
             release_ws();
             g_stats.live_alloc_bytes = g_live_bytes.load();
             return fail(WS_ENOMEM, "digit scratch allocation failed");
@@ -374,7 +416,7 @@ int execute(const ws_args &a, const PlanKey &key) {
             g_live_bytes += scratch_bytes;
     }
     const int rc = run_plan(*plan, a, ws, stream, (a.flags & WS_FLAG_TRACE) != 0, scratch,
-                            scratch_bytes);
+                            scratch_bytes, dexec.get());
     if (scratch) {
         (void)hipFreeAsync(scratch, stream);
         g_live_bytes -= scratch_bytes;
@@ -430,25 +472,26 @@ int execute_noalloc(const ws_args &a, const PlanKey &key) {
     }
     hipStream_t stream = a.stream ? static_cast<hipStream_t>(a.stream) : g_stream.load();
     const size_t ws_bytes = ((size_t)plan->ws_elems * 8u + 255) & ~size_t(255);
-    size_t scratch_bytes = 0;
-    if (a.base == WS_BASE_I8_LIMBS)
-        for (const OpDesc &op : plan->ops)
-            if (op.kind == WS_OP_GEMM)
-                scratch_bytes = std::max(scratch_bytes,
-                                         digit_scratch_bytes(op.a.rows, op.b.cols, op.a.cols));
+    void *base = nullptr;
+    const int st = noalloc_scratch(&base);
+    if (st != WS_OK)
+        return st;
+    unsigned char *b = static_cast<unsigned char *>(base);
+    std::shared_ptr<const DigitExec> dexec;
+    try {
+        dexec = exec_list(*plan, a, ws_bytes ? b : nullptr);
+    } catch (const std::exception &e) {
+        return fail(WS_ENOMEM, std::string("digit execution list: ") + e.what());
+    }
+    const size_t scratch_bytes = digit_scratch_need(*plan, a, dexec.get());
     const size_t need = ws_bytes + scratch_bytes;
     if (need > (size_t)WSMUL_NOALLOC_SCRATCH_BYTES)
         return fail(WS_ENOMEM, "the product needs " + std::to_string(need) +
                                    " bytes of workspace and digit scratch; the static scratch of "
                                    "wsmul_mod_p_noalloc holds " +
                                    std::to_string((size_t)WSMUL_NOALLOC_SCRATCH_BYTES));
-    void *base = nullptr;
-    const int st = noalloc_scratch(&base);
-    if (st != WS_OK)
-        return st;
-    unsigned char *b = static_cast<unsigned char *>(base);
     const int rc = run_plan(*plan, a, ws_bytes ? b : nullptr, stream, false,
-                            scratch_bytes ? b + ws_bytes : nullptr, scratch_bytes);
+                            scratch_bytes ? b + ws_bytes : nullptr, scratch_bytes, dexec.get());
     fill_stats(*plan, a, g_stats);
     g_stats.internal_alloc_bytes = 0;
     g_stats.scratch_bytes = scratch_bytes;
@@ -720,9 +763,9 @@ int wsmul_plan_export(const ws_args *args, ws_op_desc *ops, int64_t cap, int64_t
         auto plan = get_plan(key);
         if (a.base == WS_BASE_I8_LIMBS && plan->ws_elems > 0) {
             auto ex = digit_exec(*plan);
-            *count = (int64_t)ex->size();
+            *count = (int64_t)ex->ops.size();
             for (int64_t i = 0; i < cap && i < *count; ++i) {
-                const ExecOp &e = (*ex)[i];
+                const ExecOp &e = ex->ops[i];
                 ops[i] = e.op;
                 for (int k = 0; k < e.op.nin; ++k)
                     ops[i].in[k].form = e.in_enc[k];

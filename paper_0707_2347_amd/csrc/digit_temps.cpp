@@ -295,24 +295,127 @@ void assign_encodings(std::vector<ExecOp> &ops) {
     }
 }
 
+// Inputs read as planes.  When the plan never writes A (B), every view of
+// it that a product takes as its left (right) operand, or a digit addition
+// group reads, and that covers whole tiles, can be read from digit planes of
+// the whole input, split once at the start of the call: a product skips its
+// split of that view and a group reads 3 bytes per entry instead of 8.  It
+// is done for an input when the bytes it spares exceed the whole split's.
+void mark_input_planes(DigitExec &x, const PlanKey &key) {
+    constexpr int A_ROLE = 1, B_ROLE = 2;
+    bool writes_a = false, writes_b = false;
+    for (const ExecOp &e : x.ops)
+        for (int o = 0; o < e.op.nout; ++o) {
+            writes_a = writes_a || e.op.out[o].buf == WS_BUF_A;
+            writes_b = writes_b || e.op.out[o].buf == WS_BUF_B;
+        }
+    auto aligned = [&](const View &v, int role) {
+        const int64_t ld = role == A_ROLE ? key.lda : key.ldb;
+        if (v.rows <= 0 || v.cols <= 0 || v.ld != ld || ld <= 0)
+            return false;
+        const int64_t r0 = v.off / ld, c0 = v.off % ld;
+        if (role == A_ROLE)
+            return r0 % TILE_ROWS == 0 && v.rows % TILE_ROWS == 0 && c0 % KSTEP_COLS == 0 &&
+                   v.cols % KSTEP_COLS == 0;
+        return c0 % TILE_ROWS == 0 && v.cols % TILE_ROWS == 0 && r0 % KSTEP_COLS == 0 &&
+               v.rows % KSTEP_COLS == 0;
+    };
+    for (int role = A_ROLE; role <= B_ROLE; ++role) {
+        const int buf = role == A_ROLE ? WS_BUF_A : WS_BUF_B;
+        if (role == A_ROLE ? writes_a : writes_b)
+            continue;
+        double spared = 0.0;
+        for (const ExecOp &e : x.ops) {
+            const OpDesc &op = e.op;
+            if (op.kind == WS_OP_GEMM) {
+                const View &v = role == A_ROLE ? op.a : op.b;
+                if (v.buf == buf && aligned(v, role))
+                    spared += 11.0 * (double)v.rows * (double)v.cols;
+            } else if (lin_capable(op)) {
+                for (int i = 0; i < op.nin; ++i)
+                    if (op.in[i].buf == buf && aligned(op.in[i], role))
+                        spared += 5.0 * (double)op.in[i].rows * (double)op.in[i].cols;
+            }
+        }
+        const double whole = 11.0 * (double)key.k * (double)(role == A_ROLE ? key.m : key.n);
+        if (spared <= whole)
+            continue;
+        for (ExecOp &e : x.ops) {
+            OpDesc &op = e.op;
+            if (op.kind == WS_OP_GEMM) {
+                const View &v = role == A_ROLE ? op.a : op.b;
+                if (v.buf == buf && aligned(v, role))
+                    (role == A_ROLE ? e.pre_a : e.pre_b) = true;
+            } else if (lin_capable(op)) {
+                for (int i = 0; i < op.nin; ++i)
+                    if (op.in[i].buf == buf && aligned(op.in[i], role))
+                        e.in_enc[i] = (int8_t)role;
+            }
+        }
+        if (role == A_ROLE) {
+            x.split_a = true;
+            x.a_rows = (key.m + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
+            x.a_kp = (std::max<int64_t>(key.k, 1) + KSTEP_COLS - 1) / KSTEP_COLS * KSTEP_COLS;
+        } else {
+            x.split_b = true;
+            x.b_cols = (key.n + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS;
+            x.b_kp = (std::max<int64_t>(key.k, 1) + KSTEP_COLS - 1) / KSTEP_COLS * KSTEP_COLS;
+        }
+    }
+    x.input_bytes = (size_t)(3 * (x.a_rows * x.a_kp + x.b_cols * x.b_kp));
+    x.split_bytes = 0;
+    for (const ExecOp &e : x.ops)
+        if (e.op.kind == WS_OP_GEMM) {
+            const int64_t M = e.op.a.rows, K = std::max<int64_t>(e.op.a.cols, 1), N = e.op.b.cols;
+            const int64_t Kp = (K + KSTEP_COLS - 1) / KSTEP_COLS * KSTEP_COLS;
+            const size_t own =
+                (e.pre_a ? 0 : (size_t)(3 * ((M + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS) * Kp)) +
+                (e.pre_b ? 0 : (size_t)(3 * ((N + TILE_ROWS - 1) / TILE_ROWS * TILE_ROWS) * Kp));
+            x.split_bytes = std::max(x.split_bytes, own);
+        }
+}
+
+// Where a view with a form keeps its planes.
+struct PlaneAt {
+    const int8_t *ptr;
+    int64_t ld, plane;      // inner length of the plane rows (K), bytes per plane
+};
+
+PlaneAt plane_at(const DigitExec &x, const View &v, int role, const DevBufs &bufs) {
+    if (v.buf == WS_BUF_W) {
+        const int8_t *p = static_cast<const int8_t *>(bufs.ptr[WS_BUF_W]) + v.off * 8;
+        return {p, role == 1 ? v.cols : v.rows, v.rows * v.cols};
+    }
+    const int8_t *base = static_cast<const int8_t *>(bufs.scratch);
+    constexpr int64_t BLOCK = TILE_ROWS * KSTEP_COLS;
+    const int64_t r0 = v.off / v.ld, c0 = v.off % v.ld;
+    if (v.buf == WS_BUF_A)      // rows r0.., inner c0..
+        return {base + ((r0 / TILE_ROWS) * (x.a_kp / KSTEP_COLS) + c0 / KSTEP_COLS) * BLOCK,
+                x.a_kp, x.a_rows * x.a_kp};
+    const int8_t *bp = base + 3 * x.a_rows * x.a_kp;   // B: inner rows r0.., columns c0..
+    return {bp + ((c0 / TILE_ROWS) * (x.b_kp / KSTEP_COLS) + r0 / KSTEP_COLS) * BLOCK, x.b_kp,
+            x.b_cols * x.b_kp};
+}
+
 }  // namespace
 
-std::shared_ptr<const std::vector<ExecOp>> digit_exec(const Plan &plan) {
+std::shared_ptr<const DigitExec> digit_exec(const Plan &plan) {
     std::lock_guard<std::mutex> lock(plan.exec_mu);
     if (plan.exec_cache)
-        return std::static_pointer_cast<const std::vector<ExecOp>>(plan.exec_cache);
-    auto ops = std::make_shared<std::vector<ExecOp>>();
-    ops->reserve(plan.ops.size());
+        return std::static_pointer_cast<const DigitExec>(plan.exec_cache);
+    auto x = std::make_shared<DigitExec>();
+    x->ops.reserve(plan.ops.size());
     for (const OpDesc &op : plan.ops) {
         ExecOp e{};
         e.op = op;
-        ops->push_back(e);
+        x->ops.push_back(e);
     }
-    extract_epilogue_rows(*ops);
-    split_heavy_epilogues(*ops);
-    assign_encodings(*ops);
-    plan.exec_cache = ops;
-    return ops;
+    extract_epilogue_rows(x->ops);
+    split_heavy_epilogues(x->ops);
+    assign_encodings(x->ops);
+    mark_input_planes(*x, plan.key);
+    plan.exec_cache = x;
+    return x;
 }
 
 bool exec_uses_digits(const ExecOp &e) {
@@ -325,12 +428,45 @@ bool exec_uses_digits(const ExecOp &e) {
     return false;
 }
 
+hipError_t launch_input_splits(const DigitExec &x, const DevBufs &bufs, int64_t lda, int64_t ldb,
+                               int64_t m, int64_t k, int64_t n, int dtype, int64_t p,
+                               hipStream_t stream) {
+    int8_t *base = static_cast<int8_t *>(bufs.scratch);
+    if ((x.split_a || x.split_b) && (!base || bufs.scratch_bytes < x.input_bytes))
+        return hipErrorInvalidValue;
+    hipError_t e = hipSuccess;
+    if (x.split_a)
+        e = launch_split_rows(bufs.ptr[WS_BUF_A], lda, m, k, base, dtype, p, stream);
+    if (e == hipSuccess && x.split_b)
+        e = launch_split_cols(bufs.ptr[WS_BUF_B], ldb, k, n, base + 3 * x.a_rows * x.a_kp, dtype,
+                              p, stream);
+    return e;
+}
+
+hipError_t launch_exec_gemm(const DigitExec &x, const ExecOp &e, const DevBufs &bufs, int dtype,
+                            int64_t p, hipStream_t stream) {
+    const OpDesc &op = e.op;
+    PlaneRef ra{}, rb{};
+    if (e.pre_a) {
+        const PlaneAt at = plane_at(x, op.a, 1, bufs);
+        ra = {at.ptr, at.plane, at.ld / KSTEP_COLS};
+    }
+    if (e.pre_b) {
+        const PlaneAt at = plane_at(x, op.b, 2, bufs);
+        rb = {at.ptr, at.plane, at.ld / KSTEP_COLS};
+    }
+    DevBufs b = bufs;
+    b.split_offset = x.input_bytes;
+    return launch_gemm_limbs(op, b, dtype, p, stream, e.pre_a ? &ra : nullptr,
+                             e.pre_b ? &rb : nullptr);
+}
+
 // One addition group with digit-plane inputs or outputs.  Its outputs fall
 // into independent parts (outputs that share no input, as the S and T halves
 // of a Table 1 pre-addition); each part is its own launch, so a workgroup
 // holds only the part's inputs in LDS and more of them fit on a CU.
-hipError_t launch_exec_add(const ExecOp &e, const DevBufs &bufs, int dtype, int64_t p,
-                           hipStream_t stream) {
+hipError_t launch_exec_add(const DigitExec &x, const ExecOp &e, const DevBufs &bufs, int dtype,
+                           int64_t p, hipStream_t stream) {
     const OpDesc &op = e.op;
     int part[WS_MAX_OUT];
     for (int o = 0; o < op.nout; ++o)
@@ -362,9 +498,15 @@ hipError_t launch_exec_add(const ExecOp &e, const DevBufs &bufs, int dtype, int6
     auto io = [&](const View &v, int kind) {
         DigitIO d{};
         d.kind = kind;
-        d.ptr = static_cast<const char *>(bufs.ptr[v.buf]) + v.off * 8;
-        d.ld = kind == 0 ? v.ld : (kind == 1 ? v.cols : v.rows);
-        d.plane = v.rows * v.cols;
+        if (kind == 0) {
+            d.ptr = static_cast<const char *>(bufs.ptr[v.buf]) + v.off * 8;
+            d.ld = v.ld;
+        } else {
+            const PlaneAt at = plane_at(x, v, kind, bufs);
+            d.ptr = at.ptr;
+            d.ld = at.ld;
+            d.plane = at.plane;
+        }
         return d;
     };
     for (int r = 0; r < op.nout; ++r) {

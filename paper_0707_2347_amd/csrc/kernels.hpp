@@ -39,6 +39,7 @@ struct DevBufs {
     void *ptr[4];
     void *scratch;          // digit planes of the INT8 base (WS_BASE_I8_LIMBS)
     size_t scratch_bytes;
+    size_t split_offset = 0;  // where a base product's own splits go in scratch
 };
 
 // One fused group of addition rows (elementwise, HBM-bound).

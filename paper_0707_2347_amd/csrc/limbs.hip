@@ -250,9 +250,11 @@ typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 struct DigitParams {
     GemmParams g;              // shapes, modulus, alpha and the fused epilogue
-    const int8_t *Ad;          // 3 planes, Mp x Kp
-    const int8_t *Bd;          // 3 planes, Np x Kp
+    const int8_t *Ad;          // 3 planes; tile (row-tile i, K-step t) at (i * a_kstride + t) * 8 KB
+    const int8_t *Bd;          // 3 planes, the same for B's column tiles
     int64_t Mp, Np, Kp;
+    int64_t a_plane, b_plane;  // bytes from one digit's plane to the next
+    int64_t a_kstride, b_kstride;  // K-steps per row of tiles in the planes read
     double c24;                // 2^24 mod p
 };
 
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(128 * WN) void gemm_digits_kernel(DigitParams D) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave / WN, wn = wave % WN;
     const int li = lane & 15, g = lane >> 4;
-    const int64_t plA = D.Mp * D.Kp, plB = D.Np * D.Kp;
+    const int64_t plA = D.a_plane, plB = D.b_plane;
 
     // 48 load instructions per K-step (2 operands x 3 digits x 8 blocks of
     // 16 rows), LPW per wave.  The planes are tiled (one contiguous, already
@@ -308,8 +310,8 @@ __global__ __launch_bounds__(128 * WN) void gemm_digits_kernel(DigitParams D) {
         for (int j = 0; j < LPW; ++j) {
             const int i = wave + WAVES * j;
             const int op = i / 24, d = (i % 24) / 8, blk = i % 8;
-            const int8_t *src = op == 0 ? D.Ad + d * plA + ((int64_t)tm * ksteps + t) * PLANE
-                                        : D.Bd + d * plB + ((int64_t)tn * ksteps + t) * PLANE;
+            const int8_t *src = op == 0 ? D.Ad + d * plA + ((int64_t)tm * D.a_kstride + t) * PLANE
+                                        : D.Bd + d * plB + ((int64_t)tn * D.b_kstride + t) * PLANE;
             __builtin_amdgcn_global_load_lds(src + blk * 1024 + 16 * lane, &lds[st][op][d][blk * 1024], 16, 0, 0);
         }
     };
@@ -443,14 +445,50 @@ hipError_t launch_lin_digits(const LinDigitsParams &L, int dtype, hipStream_t st
     return hipGetLastError();
 }
 
+hipError_t launch_split_rows(const void *X, int64_t ld, int64_t R, int64_t K, int8_t *planes,
+                             int dtype, int64_t p, hipStream_t stream) {
+    if (R <= 0)
+        return hipSuccess;
+    // K = 0 still writes one K-step of zero digits: the product reads it
+    const int64_t Rp = round_up(R, TILE), Kp = round_up(std::max<int64_t>(K, 1), KSTEP);
+    const double pd = (double)p, half = std::floor(pd / 2.0);
+    const uint32_t blocks = (uint32_t)((Rp / TILE) * (Kp / KSTEP));
+    const int vec2 = (ld % 2 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0) ? 1 : 0;
+    if (dtype == WS_I64)
+        ws_launch(split_rows_kernel<int64_t>, dim3(blocks), dim3(256), 0, stream,
+                  static_cast<const int64_t *>(X), ld, R, K, Rp, Kp, planes, pd, half, vec2);
+    else
+        ws_launch(split_rows_kernel<double>, dim3(blocks), dim3(256), 0, stream,
+                  static_cast<const double *>(X), ld, R, K, Rp, Kp, planes, pd, half, vec2);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_cols(const void *X, int64_t ld, int64_t K, int64_t N, int8_t *planes,
+                             int dtype, int64_t p, hipStream_t stream) {
+    if (N <= 0)
+        return hipSuccess;
+    const int64_t Np = round_up(N, TILE), Kp = round_up(std::max<int64_t>(K, 1), KSTEP);
+    const double pd = (double)p, half = std::floor(pd / 2.0);
+    const dim3 grid((uint32_t)(Kp / 64), (uint32_t)(Np / 64));
+    if (dtype == WS_I64)
+        ws_launch(split_cols_kernel<int64_t>, grid, dim3(256), 0, stream,
+                  static_cast<const int64_t *>(X), ld, K, N, Np, Kp, planes, pd, half);
+    else
+        ws_launch(split_cols_kernel<double>, grid, dim3(256), 0, stream,
+                  static_cast<const double *>(X), ld, K, N, Np, Kp, planes, pd, half);
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtype, int64_t p,
-                             hipStream_t stream, bool pre_a, bool pre_b) {
+                             hipStream_t stream, const PlaneRef *pa, const PlaneRef *pb) {
     const int64_t M = op.a.rows, K = op.a.cols, N = op.b.cols;
     if (M == 0 || N == 0)
         return hipSuccess;
     if (K > 32768 || !limbs_supported(p))
         return hipErrorInvalidValue;
-    if (!bufs.scratch || bufs.scratch_bytes < digit_scratch_bytes(M, N, K))
+    const size_t own = (pa ? 0 : 3 * (size_t)round_up(M, TILE) * round_up(std::max<int64_t>(K, 1), KSTEP)) +
+                       (pb ? 0 : 3 * (size_t)round_up(N, TILE) * round_up(std::max<int64_t>(K, 1), KSTEP));
+    if (own && (!bufs.scratch || bufs.scratch_bytes < bufs.split_offset + own))
         return hipErrorInvalidValue;
     const size_t esz = 8;
     DigitParams D{};
@@ -477,49 +515,32 @@ hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtyp
     D.Mp = round_up(M, TILE);
     D.Np = round_up(N, TILE);
     D.Kp = round_up(std::max<int64_t>(K, 1), KSTEP);
-    // Operands already held as digit planes at their views (pre_a, pre_b:
-    // whole tiles, so the padded sizes are the sizes) are read in place.
-    if ((pre_a && (M % TILE || K % KSTEP)) || (pre_b && (N % TILE || K % KSTEP)))
+    // Operands already held as digit planes (whole tiles, so the padded
+    // sizes are the sizes) are read where they are; the others are split
+    // into the scratch area past bufs.split_offset.
+    if ((pa && (M % TILE || K % KSTEP)) || (pb && (N % TILE || K % KSTEP)))
         return hipErrorInvalidValue;
-    int8_t *Ad = static_cast<int8_t *>(bufs.scratch);
-    int8_t *Bd = Ad + 3 * D.Mp * D.Kp;
-    if (pre_a)
-        Ad = static_cast<int8_t *>(bufs.ptr[op.a.buf]) + op.a.off * esz;
-    if (pre_b)
-        Bd = static_cast<int8_t *>(bufs.ptr[op.b.buf]) + op.b.off * esz;
-    D.Ad = Ad;
-    D.Bd = Bd;
+    int8_t *own_a = static_cast<int8_t *>(bufs.scratch) + bufs.split_offset;
+    int8_t *own_b = own_a + (pa ? 0 : 3 * D.Mp * D.Kp);
+    D.Ad = pa ? pa->ptr : own_a;
+    D.Bd = pb ? pb->ptr : own_b;
+    D.a_plane = pa ? pa->plane : D.Mp * D.Kp;
+    D.b_plane = pb ? pb->plane : D.Np * D.Kp;
+    D.a_kstride = pa ? pa->kstride : D.Kp / KSTEP;
+    D.b_kstride = pb ? pb->kstride : D.Kp / KSTEP;
     D.c24 = (double)((int64_t(1) << 24) % p);
     const void *Aop = static_cast<const char *>(bufs.ptr[op.a.buf]) + op.a.off * esz;
     const void *Bop = static_cast<const char *>(bufs.ptr[op.b.buf]) + op.b.off * esz;
-    const uint32_t blocks_a = (uint32_t)((D.Mp / TILE) * (D.Kp / KSTEP));
-    const dim3 grid_b((uint32_t)(D.Kp / 64), (uint32_t)(D.Np / 64));
     // Traced runs time the splits on their own event pair.
     const LaunchTiming timing = launch_timing();
     if (timing.split_start)
         launch_timing() = LaunchTiming{timing.split_start, timing.split_stop, false, nullptr, nullptr};
-    const int vec2 = (op.a.ld % 2 == 0 && reinterpret_cast<uintptr_t>(Aop) % 16 == 0) ? 1 : 0;
-    if (dtype == WS_I64) {
-        if (!pre_a)
-            ws_launch(split_rows_kernel<int64_t>, dim3(blocks_a), dim3(256), 0, stream,
-                      static_cast<const int64_t *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
-                      P.p, P.half, vec2);
-        if (!pre_b)
-            ws_launch(split_cols_kernel<int64_t>, grid_b, dim3(256), 0, stream,
-                      static_cast<const int64_t *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
-                      P.p, P.half);
-    } else {
-        if (!pre_a)
-            ws_launch(split_rows_kernel<double>, dim3(blocks_a), dim3(256), 0, stream,
-                      static_cast<const double *>(Aop), op.a.ld, M, K, D.Mp, D.Kp, Ad,
-                      P.p, P.half, vec2);
-        if (!pre_b)
-            ws_launch(split_cols_kernel<double>, grid_b, dim3(256), 0, stream,
-                      static_cast<const double *>(Bop), op.b.ld, K, N, D.Np, D.Kp, Bd,
-                      P.p, P.half);
-    }
+    hipError_t e = hipSuccess;
+    if (!pa)
+        e = launch_split_rows(Aop, op.a.ld, M, K, own_a, dtype, p, stream);
+    if (e == hipSuccess && !pb)
+        e = launch_split_cols(Bop, op.b.ld, K, N, own_b, dtype, p, stream);
     launch_timing() = timing;
-    hipError_t e = hipGetLastError();
     if (e != hipSuccess)
         return e;
     P.tiles_m = (int32_t)(D.Mp / TILE);

@@ -65,10 +65,29 @@ def run(ops, bufs, p):
     with a value that is no residue: a read of such a block as residues, a
     read of planes nobody wrote, or a group that reads a view in one form and
     writes it in another (on the device its workgroups would overwrite bytes
-    others still read) fails."""
+    others still read) fails.  Views of A and B with a form read the inputs
+    as they were at the start (planes of the whole input)."""
     planes = {}
+    # Views of A or B with a form read planes of the whole input, split at
+    # the start of the call: the plan must never write that input.
+    originals = [bufs[0].copy(), bufs[1].copy()]
+    views = [v for op in ops for v in ([op.a, op.b] if op.kind == capi.WS_OP_GEMM else []) +
+             [op.in_[i] for i in range(op.nin)]]
+    for b in (capi.WS_BUF_A, capi.WS_BUF_B):
+        if any(v.form and v.buf == b for v in views):
+            assert not any(op.out[o].buf == b for op in ops for o in range(op.nout)), \
+                "an input read as planes is written"
 
     def read(v):
+        if v.form and v.buf in (capi.WS_BUF_A, capi.WS_BUF_B):
+            r0, c0 = divmod(v.off, v.ld)
+            if v.form == capi.WS_FORM_DIGITS_A:
+                assert v.buf == capi.WS_BUF_A and r0 % 128 == 0 and v.rows % 128 == 0 and \
+                    c0 % 64 == 0 and v.cols % 64 == 0, "A planes need whole tiles"
+            else:
+                assert v.buf == capi.WS_BUF_B and c0 % 128 == 0 and v.cols % 128 == 0 and \
+                    r0 % 64 == 0 and v.rows % 64 == 0, "B planes need whole tiles"
+            return _view(originals[v.buf], v).copy()
         if v.form:
             _check_planes_view(v, v.form)
             assert (_key(v), v.form) in planes, "digit planes read before they were written"

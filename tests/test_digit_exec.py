@@ -97,17 +97,20 @@ def test_execution_list_reproduces_oracle(schedule, shape, levels, acc, digits, 
 def test_table1_execution_list():
     """Table 1, one level: every temporary is held as digit planes.  S and T
     blocks are written as planes by the pre-additions (T4 by a group moved
-    out of P1's epilogue), P5, P6 and P7 read both operands as planes, P3 its
-    A operand and P4 its B operand; P1 and P2 read inputs.  P1's epilogue
-    (four inputs, three outputs besides P1 itself) moves into a group of
-    residues right after it that reads P1 back from X."""
+    out of P1's epilogue); the quadrants of A and B are read from planes of
+    the whole inputs, split once, by the pre-additions and by the products.
+    P1's epilogue (four inputs, three outputs besides P1 itself) moves into a
+    group of residues right after it that reads P1 back from X."""
     info, ops = _export(capi.WS_TWO_TEMP, 512, 512, 512, 65521, 1, 0, 1)
     _, plain = _export(capi.WS_TWO_TEMP, 512, 512, 512, 65521, 1, 0, 1,
                        base=capi.WS_BASE_F64_MFMA)
     assert len(ops) == len(plain) + 2 == 13
     gemms = [op for op in ops if op.kind == capi.WS_OP_GEMM]
-    assert [(g.a.form, g.b.form) for g in gemms] == [(1, 2), (1, 2), (1, 2), (1, 0), (0, 0),
-                                                   (0, 2), (0, 0)]
+    # every operand is read as planes: temporaries in W, input quadrants from
+    # the planes of the whole A and B (split once)
+    assert [(g.a.form, g.b.form) for g in gemms] == [(1, 2)] * 7
+    assert [(g.a.buf, g.b.buf) for g in gemms] == [(3, 3), (3, 3), (3, 3), (3, 1), (0, 1),
+                                                   (0, 3), (0, 1)]
     assert all(g.nout == 1 for g in gemms[:5])
     adds = [op for op in ops if op.kind == capi.WS_OP_ADD]
     assert len(adds) == 6
@@ -116,10 +119,13 @@ def test_table1_execution_list():
     for op in digit:
         assert all(op.out[o].form for o in range(op.nout))
     after_p1 = ops[ops.index(next(o for o in ops if o.kind == capi.WS_OP_GEMM and
-                                  (o.a.form, o.b.form) == (0, 0))) + 1]
+                                  (o.a.buf, o.b.buf) == (0, 1))) + 1]
     assert after_p1.kind == capi.WS_OP_ADD and after_p1.nout == 3 and after_p1.nin == 5
     assert after_p1.in_[0].buf == capi.WS_BUF_W and not any(
         after_p1.in_[i].form for i in range(after_p1.nin))
+    # the pre-additions read the input quadrants as planes too
+    for op in digit:
+        assert all(op.in_[i].form for i in range(op.nin))
     assert _forms(plain) == 0
 
 

@@ -98,17 +98,17 @@ def test_digit_temporaries(schedule, shape, levels, acc, p, dtype):
 
 
 def test_table1_uses_digits_for_every_temporary():
-    """Table 1, one level, at 2048: the seven products split only the
-    operands that are inputs (P1, P2: both; P3: B22; P4: A22), so 2 + 2 + 1 + 1
-    splits and 8 operands read as planes; five addition groups are digit
-    ones (S3/T3, S1/T1, S2/T2, S4, and T4 moved out of P1's epilogue) and
-    one, P1's post-additions moved after it, runs on residues."""
+    """Table 1, one level, at 2048: A and B are split once each, and all 14
+    product operands are read as planes (temporaries in W, input quadrants
+    from the whole inputs' planes); five addition groups are digit ones
+    (S3/T3, S1/T1, S2/T2, S4, and T4 moved out of P1's epilogue) and one,
+    P1's post-additions moved after it, runs on residues."""
     p = 1048573
     (A, B, C), (_, _, C2), tr = _run(capi.WS_TWO_TEMP, 2048, 2048, 2048, 1, p, 1, 0,
                                      capi.WS_F64, 11)
     assert np.array_equal(C2, ref.matmul_mod_p(A, B, None, 1, 0, p))
     assert tr.gemm_launches == 7
-    assert tr.split_launches == 6 and tr.unsplit_operands == 8
+    assert tr.split_launches == 2 and tr.unsplit_operands == 14
     assert tr.add_launches == 6 and tr.digit_adds == 5
 
 
