@@ -246,6 +246,88 @@ __global__ __launch_bounds__(256) void lin_digits_kernel(LinDigitsParams L) {
     }
 }
 
+// Addition groups whose digit-plane operands all have one role, and whose
+// residue operands (if any) are in the A role: each thread takes one 16-byte
+// chunk position of the tiled layout (16 consecutive inner indices of one
+// plane row) in every operand, so nothing is transposed and no LDS is used.
+// 512 consecutive threads cover one 128 x 64 block, 8 KB of every plane.
+template <typename T, int NIN>
+__global__ __launch_bounds__(256) void lin_chunks_kernel(LinDigitsParams L, int role) {
+    const int64_t inner = role == 1 ? L.Cc : L.R;      // K-direction length of the planes
+    const int64_t ksteps = inner / KSTEP;
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t blk = g / 512, within = g % 512;
+    const int64_t pt = blk / ksteps, kt = blk % ksteps;
+    const int rr = (int)(within / 4), slot = (int)(within % 4);
+    const int64_t prow = pt * TILE + rr;                    // plane row (A: row, B: column)
+    const int lc = slot ^ ((rr >> 2) & 3);                  // logical 16-wide chunk
+    const int64_t col0 = kt * KSTEP + 16 * lc;              // first inner index of the chunk
+    const int32_t pi = (int32_t)L.p;
+    int32_t val[NIN][16];
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) {
+        const DigitIO &io = L.in[i];
+        if (io.kind == 0) {                                 // A role: row prow, columns col0..
+            const T *X = static_cast<const T *>(io.ptr) + prow * io.ld + col0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                val[i][e] = (int32_t)to_f64(X[e]);
+        } else {
+            const int8_t *b = static_cast<const int8_t *>(io.ptr) +
+                              (pt * (io.ld / KSTEP) + kt) * (TILE * KSTEP) + within * 16;
+            union {
+                uint4 u;
+                int8_t d[16];
+            } x0, x1, x2;
+            x0.u = *reinterpret_cast<const uint4 *>(b);
+            x1.u = *reinterpret_cast<const uint4 *>(b + io.plane);
+            x2.u = *reinterpret_cast<const uint4 *>(b + 2 * io.plane);
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                val[i][e] = undigit(x0.d[e], x1.d[e], x2.d[e], pi);
+        }
+    }
+    for (int o = 0; o < L.nout; ++o) {
+        const DigitIO &io = L.out[o];
+        auto at = [&](int e) {
+            double sum = 0.0;
+#pragma unroll
+            for (int i = 0; i < NIN; ++i)
+                sum = fma(L.coef[o][i], (double)val[i][e], sum);
+            return mod_reduce(sum, L.p, L.pinv);
+        };
+        if (io.kind == 0) {
+            T *Y = static_cast<T *>(const_cast<void *>(io.ptr)) + prow * io.ld + col0;
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                Y[e] = from_f64<T>(at(e));
+        } else {
+            union {
+                uint4 u;
+                int8_t d[16];
+            } y0, y1, y2;
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                digits3(at(e), L.p, L.half, y0.d[e], y1.d[e], y2.d[e]);
+            int8_t *b = static_cast<int8_t *>(const_cast<void *>(io.ptr)) +
+                        (pt * (io.ld / KSTEP) + kt) * (TILE * KSTEP) + within * 16;
+            *reinterpret_cast<uint4 *>(b) = y0.u;
+            *reinterpret_cast<uint4 *>(b + io.plane) = y1.u;
+            *reinterpret_cast<uint4 *>(b + 2 * io.plane) = y2.u;
+        }
+    }
+}
+
+template <typename T>
+void launch_chunks(const LinDigitsParams &P, int role, uint32_t blocks, hipStream_t stream) {
+    switch (P.nin) {
+    case 1: ws_launch(lin_chunks_kernel<T, 1>, dim3(blocks), dim3(256), 0, stream, P, role); break;
+    case 2: ws_launch(lin_chunks_kernel<T, 2>, dim3(blocks), dim3(256), 0, stream, P, role); break;
+    case 3: ws_launch(lin_chunks_kernel<T, 3>, dim3(blocks), dim3(256), 0, stream, P, role); break;
+    default: ws_launch(lin_chunks_kernel<T, 4>, dim3(blocks), dim3(256), 0, stream, P, role); break;
+    }
+}
+
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 struct DigitParams {
@@ -435,6 +517,28 @@ hipError_t launch_lin_digits(const LinDigitsParams &L, int dtype, hipStream_t st
     if (L.R % 64 || L.Cc % 64 || L.nin < 1 || L.nin > LD_MAX || L.nout < 1 || L.nout > LD_MAX)
         return hipErrorInvalidValue;
     LinDigitsParams P = L;
+    // One role among the digit operands, and residues only beside the A
+    // role: the chunk kernel (no transposition) takes the group.
+    int role = 0;
+    bool residues = false, mixed = false;
+    for (int i = 0; i < L.nin + L.nout; ++i) {
+        const int kind = i < L.nin ? L.in[i].kind : L.out[i - L.nin].kind;
+        if (kind == 0)
+            residues = true;
+        else if (role && role != kind)
+            mixed = true;
+        else
+            role = kind;
+    }
+    const int64_t prows = role == 1 ? L.R : L.Cc, inner = role == 1 ? L.Cc : L.R;
+    if (role && !mixed && !(residues && role != 1) && prows % TILE == 0 && inner % KSTEP == 0) {
+        const uint32_t blocks = (uint32_t)(L.R * L.Cc / 16 / 256);
+        if (dtype == WS_I64)
+            launch_chunks<int64_t>(P, role, blocks, stream);
+        else
+            launch_chunks<double>(P, role, blocks, stream);
+        return hipGetLastError();
+    }
     P.tiles_c = (int32_t)(L.Cc / 64);
     const dim3 grid((uint32_t)((L.R / 64) * (L.Cc / 64)));
     const uint32_t lds = (uint32_t)(L.nin * 64 * 65 * sizeof(int32_t));
