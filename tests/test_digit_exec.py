@@ -140,3 +140,28 @@ def test_misplaced_planes_are_caught():
             np.zeros(2 * 128 * 128, np.int64)]
     with pytest.raises(AssertionError, match="holds digit planes"):
         plan_interp.run(ops, bufs, 65521)
+
+
+@pytest.mark.parametrize("graph", ["table9", "table2"])
+@pytest.mark.parametrize("n,levels", [(256, 1), (512, 2)])
+def test_row_schedules_on_the_digit_base(graph, n, levels):
+    """Schedules given as rows (the §4 search's, tests/golden/acc_search.json)
+    run on the digit base's execution list: same result as the oracle, A and
+    B untouched, and digit planes in use."""
+    import json
+    d = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                    "acc_search.json")))[graph]
+    st, sid = capi.wsmul_register_rows([tuple(r) for r in d["library_rows"]], d["temps"])
+    assert st == capi.WS_OK
+    p = 1048573
+    A, B, C = inputs.uniform(n + levels, n, n, n, p, with_c=True)
+    args = capi.make_args(n, n, n, p, alpha=5, beta=p - 7, schedule=capi.WS_ROWS, levels=levels,
+                          blocks=sid, base=I8)
+    info, ops = capi.wsmul_plan_info(args), capi.wsmul_plan_export(args)
+    assert _forms(ops) > 0
+    rng = np.random.default_rng(n)
+    W = rng.integers(0, p, size=max(info.workspace_bytes // 8, 1))
+    bufs = [A.copy().ravel(), B.copy().ravel(), C.copy().ravel(), W]
+    plan_interp.run(ops, bufs, p)
+    assert np.array_equal(bufs[2].reshape(n, n), ref.matmul_mod_p(A, B, C, 5, p - 7, p))
+    assert np.array_equal(bufs[0].reshape(n, n), A) and np.array_equal(bufs[1].reshape(n, n), B)
