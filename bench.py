@@ -172,12 +172,14 @@ class Ctx:
         traffic = measured_traffic(self.args.workload, gemm_dominant)
         if gemm_dominant and tr.gemm_launches:
             if int8_ops:
-                # 9 digit products of 2*M*N*K int8 ops each per base product;
-                # the time is the product kernel's own (the splits are apart)
-                ops = 9.0 * gemm_flops_per
+                # nd^2 digit products of 2*M*N*K int8 ops each per base product
+                # (nd = 3 digits, 2 for p <= 65536); the time is the product
+                # kernel's own (the splits are apart)
+                nd = 2 if args.p <= 65536 else 3
+                ops = nd * nd * gemm_flops_per
                 ach = ops / (gemm_avg_ms * 1e-3) / 1e12
                 roof = {"bound": "mfma", "kernel": "gemm_digits_kernel (int8 16x16x64 matrix "
-                        "cores, 3 x 3 digit products of 2mnk int8 ops each)",
+                        "cores, %d x %d digit products of 2mnk int8 ops each)" % (nd, nd),
                         "achieved": round(ach, 2), "peak": PEAK_I8_MFMA_TOPS, "unit": "TOP/s",
                         "frac": round(ach / PEAK_I8_MFMA_TOPS, 4), "traffic": traffic,
                         "avg_launch_ms": round(gemm_avg_ms, 5), "int8_ops_per_launch": ops}

@@ -121,7 +121,9 @@ typedef enum { WS_F64 = 0, WS_I64 = 1 } ws_dtype;
 typedef enum {
     WS_BASE_AUTO = 0,        /* library choice                                      */
     WS_BASE_F64_MFMA = 1,    /* binary64 matrix cores, delayed modular reduction    */
-    WS_BASE_I8_LIMBS = 2     /* centred residues as signed 8-bit digits, int32 sums */
+    WS_BASE_I8_LIMBS = 2     /* centred residues as signed 8-bit digits, int32 sums:
+                                three digits (nine digit products), two (four) when
+                                p <= 65536; p <= 16711423 and k <= 32768 */
 } ws_base;
 
 enum {

@@ -57,8 +57,11 @@ double gemm_f64_us(int64_t M, int64_t N, int64_t K, int64_t p) {
     return std::max(7.0, flops / rate * 1e6);
 }
 
-double gemm_digits_us(int64_t M, int64_t N, int64_t K, bool pre_a = false, bool pre_b = false) {
-    const double flops = 2.0 * (double)M * (double)N * (double)K;
+double gemm_digits_us(int64_t M, int64_t N, int64_t K, int64_t p, bool pre_a = false,
+                      bool pre_b = false) {
+    // the rates are for three digits (nine digit products); two take four
+    const double nd = (double)digit_count(p);
+    const double flops = 2.0 * (double)M * (double)N * (double)K * nd * nd / 9.0;
     const int64_t tiles = ((M + 127) / 128) * ((N + 127) / 128);
     const double rate = tiles >= 16384  ? 318e12
                         : tiles >= 2048 ? 310e12
@@ -269,7 +272,7 @@ double plan_cost_us(const Plan &plan, int base) {
                 // the rates include the product's own store; every further
                 // epilogue stream adds its bytes at ~3.2 TB/s (all tiles of a
                 // round run their epilogues together, after their products)
-                t += gemm_digits_us(op.a.rows, op.b.cols, op.a.cols, e.pre_a, e.pre_b);
+                t += gemm_digits_us(op.a.rows, op.b.cols, op.a.cols, plan.key.p, e.pre_a, e.pre_b);
                 t += 8.0 * (double)(op.nin - 1 + op.nout - 1) * elems / 3.2e12 * 1e6;
             } else {
                 double per = 0.0;
@@ -285,7 +288,7 @@ double plan_cost_us(const Plan &plan, int base) {
     }
     for (const OpDesc &op : plan.ops) {
         if (op.kind == WS_OP_GEMM) {
-            t += base == WS_BASE_I8_LIMBS ? gemm_digits_us(op.a.rows, op.b.cols, op.a.cols)
+            t += base == WS_BASE_I8_LIMBS ? gemm_digits_us(op.a.rows, op.b.cols, op.a.cols, plan.key.p)
                                           : gemm_f64_us(op.a.rows, op.b.cols, op.a.cols, plan.key.p);
             t += 8.0 * (double)(op.nin - 1 + op.nout) * (double)op.out[0].rows *
                  (double)op.out[0].cols / 4.5e12 * 1e6;   // epilogue traffic

@@ -517,7 +517,7 @@ hipError_t launch_exec_add(const DigitExec &x, const ExecOp &e, const DevBufs &b
         L.Cc = op.out[0].cols;
         L.p = (double)p;
         L.pinv = 1.0 / (double)p;
-        L.half = std::floor((double)p / 2.0);
+        L.half = digit_threshold(p);
         int in_of[WS_MAX_IN];
         for (int i = 0; i < op.nin; ++i) {
             in_of[i] = -1;

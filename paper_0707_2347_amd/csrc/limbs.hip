@@ -1,9 +1,12 @@
 // Base products from signed 8-bit digits of centred residues on the INT8
 // matrix cores (v_mfma_i32_16x16x64_i8).
 //
-// A residue x in [0, p) is centred (c = x - p when x > (p-1)/2) and written
-// in balanced base 256: c = d0 + 2^8 d1 + 2^16 d2 with every digit in
-// [-128, 127] (enough for p <= 16,711,423).  The product becomes
+// A residue x in [0, p) is centred (c = x - p when x > h) and written in
+// balanced base 256: c = d0 + 2^8 d1 + 2^16 d2 with every digit in
+// [-128, 127] (enough for p <= 16,711,423; h = (p-1)/2).  For p <= 65536 the
+// threshold is h = 32639, so that c lies in [-32896, 32639], where d2 = 0:
+// two digits, and the product needs four digit products instead of nine.
+// The product becomes
 //     A*B = sum_{w=0..4} 2^(8w) * sum_{i+j=w} A_i * B_j,
 // where every digit product is exact in int32: a weight class holds at most
 // three digit products of magnitude <= K * 2^14, below 2^31 for K <= 32768.
@@ -23,6 +26,10 @@
 namespace wsmul {
 
 bool limbs_supported(int64_t p) { return p <= 16711423; }
+
+int digit_count(int64_t p) { return p <= 65536 ? 2 : 3; }
+
+double digit_threshold(int64_t p) { return p <= 65536 ? 32639.0 : std::floor((double)p / 2.0); }
 
 namespace {
 
@@ -356,14 +363,16 @@ struct DigitParams {
 #ifndef WS_I8_STAGES
 #define WS_I8_STAGES 2
 #endif
-template <typename T, int WN, int STAGES>
+template <typename T, int WN, int STAGES, int ND>
 __global__ __launch_bounds__(128 * WN) void gemm_digits_kernel(DigitParams D) {
     constexpr int PLANE = TILE * KSTEP;                     // bytes of one digit tile
     constexpr int WAVES = 2 * WN, NT = 64 * WAVES;
     constexpr int WCOLS = TILE / WN, JB = WCOLS / 16;       // wave tile columns, 16-column blocks
-    constexpr int LPW = 48 / WAVES;                         // load instructions per wave and K-step
+    constexpr int LPW = 16 * ND / WAVES;                    // load instructions per wave and K-step
     static_assert(STAGES == 2 || STAGES == 3, "two or three buffers");
-    static_assert(LPW == 6 || LPW == 12, "four or eight waves");
+    static_assert(ND == 2 || ND == 3, "two or three digits");
+    static_assert(16 * ND % WAVES == 0 && (LPW == 4 || LPW == 6 || LPW == 12),
+                  "whole load instructions per wave");
     // [stage][A|B][digit], sized for three buffers whatever STAGES is: with a
     // template-dependent extent the host compiler drops the kernel's launch
     // stub without a diagnostic.
@@ -391,7 +400,7 @@ __global__ __launch_bounds__(128 * WN) void gemm_digits_kernel(DigitParams D) {
 #pragma unroll
         for (int j = 0; j < LPW; ++j) {
             const int i = wave + WAVES * j;
-            const int op = i / 24, d = (i % 24) / 8, blk = i % 8;
+            const int op = i / (8 * ND), d = (i % (8 * ND)) / 8, blk = i % 8;
             const int8_t *src = op == 0 ? D.Ad + d * plA + ((int64_t)tm * D.a_kstride + t) * PLANE
                                         : D.Bd + d * plB + ((int64_t)tn * D.b_kstride + t) * PLANE;
             __builtin_amdgcn_global_load_lds(src + blk * 1024 + 16 * lane, &lds[st][op][d][blk * 1024], 16, 0, 0);
@@ -415,13 +424,13 @@ __global__ __launch_bounds__(128 * WN) void gemm_digits_kernel(DigitParams D) {
     // way, but this order of the 72 products measured 1.5-2% faster.
     auto compute = [&](int cur) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
+        for (int a = 0; a < ND; ++a) {
             i32x4 af[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 af[i] = frag(cur, 0, a, wm * 64 + i * 16 + li);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
+            for (int b = 0; b < ND; ++b) {
                 i32x4 bf[JB];
 #pragma unroll
                 for (int j = 0; j < JB; ++j)
@@ -460,7 +469,8 @@ __global__ __launch_bounds__(128 * WN) void gemm_digits_kernel(DigitParams D) {
             // with step t-1: a plain barrier with no fence, so that the loads
             // of step t+1 stay in flight across it.
             if (t + 1 < ksteps) {
-                if (LPW == 6) asm volatile("s_waitcnt vmcnt(6)\n\ts_barrier" ::: "memory");
+                if (LPW == 4) asm volatile("s_waitcnt vmcnt(4)\n\ts_barrier" ::: "memory");
+                else if (LPW == 6) asm volatile("s_waitcnt vmcnt(6)\n\ts_barrier" ::: "memory");
                 else asm volatile("s_waitcnt vmcnt(12)\n\ts_barrier" ::: "memory");
             } else {
                 asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
@@ -555,7 +565,7 @@ hipError_t launch_split_rows(const void *X, int64_t ld, int64_t R, int64_t K, in
         return hipSuccess;
     // K = 0 still writes one K-step of zero digits: the product reads it
     const int64_t Rp = round_up(R, TILE), Kp = round_up(std::max<int64_t>(K, 1), KSTEP);
-    const double pd = (double)p, half = std::floor(pd / 2.0);
+    const double pd = (double)p, half = digit_threshold(p);
     const uint32_t blocks = (uint32_t)((Rp / TILE) * (Kp / KSTEP));
     const int vec2 = (ld % 2 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0) ? 1 : 0;
     if (dtype == WS_I64)
@@ -572,7 +582,7 @@ hipError_t launch_split_cols(const void *X, int64_t ld, int64_t K, int64_t N, in
     if (N <= 0)
         return hipSuccess;
     const int64_t Np = round_up(N, TILE), Kp = round_up(std::max<int64_t>(K, 1), KSTEP);
-    const double pd = (double)p, half = std::floor(pd / 2.0);
+    const double pd = (double)p, half = digit_threshold(p);
     const dim3 grid((uint32_t)(Kp / 64), (uint32_t)(Np / 64));
     if (dtype == WS_I64)
         ws_launch(split_cols_kernel<int64_t>, grid, dim3(256), 0, stream,
@@ -651,10 +661,18 @@ hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtyp
     P.tiles_n = (int32_t)(D.Np / TILE);
     constexpr int WN = WS_I8_WN, ST = WS_I8_STAGES;
     const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(128 * WN);
-    if (dtype == WS_I64)
-        ws_launch(gemm_digits_kernel<int64_t, WN, ST>, grid, block, 0, stream, D);
-    else
-        ws_launch(gemm_digits_kernel<double, WN, ST>, grid, block, 0, stream, D);
+    const bool two = digit_count(p) == 2;
+    if (dtype == WS_I64) {
+        if (two)
+            ws_launch(gemm_digits_kernel<int64_t, WN, ST, 2>, grid, block, 0, stream, D);
+        else
+            ws_launch(gemm_digits_kernel<int64_t, WN, ST, 3>, grid, block, 0, stream, D);
+    } else {
+        if (two)
+            ws_launch(gemm_digits_kernel<double, WN, ST, 2>, grid, block, 0, stream, D);
+        else
+            ws_launch(gemm_digits_kernel<double, WN, ST, 3>, grid, block, 0, stream, D);
+    }
     return hipGetLastError();
 }
 

@@ -33,6 +33,10 @@ int autotune_choice(ws_args &a, bool beta_nonzero);
 
 // Base products from signed 8-bit digits of centred residues.
 bool limbs_supported(int64_t p);
+// Digits per residue (2 for p <= 65536, else 3) and the centring threshold
+// (residues above it are taken minus p) that keeps the top digit in range.
+int digit_count(int64_t p);
+double digit_threshold(int64_t p);
 size_t digit_scratch_bytes(int64_t M, int64_t N, int64_t K);
 // Digit planes an operand is read from instead of being split: tile
 // (row-tile i, K-step t) of digit d at ptr + d * plane + (i * kstride + t) * 8 KB.
