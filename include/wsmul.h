@@ -164,7 +164,8 @@ typedef struct ws_stats {
     int64_t schedule;              /* table actually run (see wsmul_schedule_name)    */
     int64_t base;                  /* base kind actually used                         */
     uint64_t scratch_bytes;        /* INT8 base: digit planes of the largest base product
-                                      (kernel scratch, not a schedule temporary)       */
+                                      and of inputs read as planes (kernel scratch,
+                                      not a schedule temporary)                        */
     uint64_t batch_phases;         /* batches: persistent launches (phases) issued     */
     uint64_t live_alloc_bytes;     /* device bytes still held by single-product calls of
                                       this process after the call returned (owned
