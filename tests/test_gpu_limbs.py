@@ -76,3 +76,23 @@ def test_digit_base_limits():
     assert capi.wsmul_mod_p_ex(a) == capi.WS_ESHAPE
     a = capi.make_args(1, 1, 1, 16711433, d, d, d, 1, 0, capi.WS_CLASSICAL, 0, base=I8)
     assert capi.wsmul_mod_p_ex(a) == capi.WS_EMODULUS
+
+
+@pytest.mark.parametrize("p", [257, 65521, 65536, 65537])
+@pytest.mark.parametrize("schedule,levels", [(capi.WS_CLASSICAL, 0), (capi.WS_TWO_TEMP, 1)])
+def test_two_digit_boundary(p, schedule, levels):
+    """p <= 65536 runs on two digits, residues above 32639 taken minus p;
+    65537 is the smallest modulus on three.  Entries at the centring
+    threshold and at the ends of the range, through the classical product
+    and through Table 1 with digit-plane temporaries."""
+    m = k = n = 512
+    print("two-digit boundary", p, schedule, flush=True)
+    h = (p - 1) // 2
+    pick = np.array(sorted({0, 1, 255, 256, min(32639, p - 1), min(32640, p - 1), h, h + 1, p - 1}),
+                    dtype=np.int64)
+    rng = np.random.default_rng(p + levels)
+    A = pick[rng.integers(0, len(pick), size=(m, k))]
+    B = pick[rng.integers(0, len(pick), size=(k, n))]
+    st, C2, _, _ = call(schedule, A, B, None, 1, 0, p, levels, base=I8)
+    assert st == capi.WS_OK, capi.wsmul_last_error()
+    assert np.array_equal(C2, ref.matmul_mod_p(A, B, None, 1, 0, p))
