@@ -661,15 +661,18 @@ hipError_t launch_gemm_limbs(const ws_op_desc &op, const DevBufs &bufs, int dtyp
     P.tiles_n = (int32_t)(D.Np / TILE);
     constexpr int WN = WS_I8_WN, ST = WS_I8_STAGES;
     const dim3 grid((uint32_t)(P.tiles_m * P.tiles_n)), block(128 * WN);
+    // Two digits load two thirds as much per K-step; there three buffers
+    // (loads two steps ahead) measured 2% faster at 16384^3, with three
+    // digits 8% slower.
     const bool two = digit_count(p) == 2;
     if (dtype == WS_I64) {
         if (two)
-            ws_launch(gemm_digits_kernel<int64_t, WN, ST, 2>, grid, block, 0, stream, D);
+            ws_launch(gemm_digits_kernel<int64_t, WN, 3, 2>, grid, block, 0, stream, D);
         else
             ws_launch(gemm_digits_kernel<int64_t, WN, ST, 3>, grid, block, 0, stream, D);
     } else {
         if (two)
-            ws_launch(gemm_digits_kernel<double, WN, ST, 2>, grid, block, 0, stream, D);
+            ws_launch(gemm_digits_kernel<double, WN, 3, 2>, grid, block, 0, stream, D);
         else
             ws_launch(gemm_digits_kernel<double, WN, ST, 3>, grid, block, 0, stream, D);
     }
