@@ -13,8 +13,11 @@
 // An epilogue row that does not read the product (Table 1 forms T4 in the
 // epilogue of P1) is moved into an addition group of its own just before
 // the product, so that the temporary it reads and the one it writes qualify
-// too; heavy epilogues move into a group after the product.  The analysis
-// runs once per plan and is kept with it.
+// too; heavy epilogues move into a group after the product.  When the plan
+// never writes A (B), the whole input is split into planes once at the start
+// of the call and the products and groups read its quadrants from there.
+// The analysis runs once per plan and is kept with it; wsmul_plan_export
+// shows the result as view forms.
 #include <algorithm>
 #include <array>
 #include <cmath>
