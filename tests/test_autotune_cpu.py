@@ -157,3 +157,23 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_digit_base_choices_at_16384():
+    """The choices the measurements support at 16384^3 (same-box pairs in the
+    design record): Table 1 at one level on the 8-bit digit base for C = AB mod
+    1048573 (temporaries and inputs held as digit planes, 2-7% ahead of the
+    classical digit product), the classical digit product for C <- AB + C (a
+    tie with Table 2, decided for the schedule without temporaries), and the
+    classical product with two digits mod 65521 (where a level loses)."""
+    st, sched, lev, base, _ = capi.wsmul_autotune(16384, 16384, 16384, 1048573)
+    assert st == capi.WS_OK and (sched, lev, base) == (capi.WS_TWO_TEMP, 1,
+                                                        capi.WS_BASE_I8_LIMBS)
+    st, sched, lev, base, _ = capi.wsmul_autotune(16384, 16384, 16384, 1048573, beta=3)
+    assert st == capi.WS_OK and (sched, base) == (capi.WS_CLASSICAL, capi.WS_BASE_I8_LIMBS)
+    st, sched, lev, base, _ = capi.wsmul_autotune(16384, 16384, 16384, 65521)
+    assert st == capi.WS_OK and (sched, base) == (capi.WS_CLASSICAL, capi.WS_BASE_I8_LIMBS)
+    # binary64 only: Winograd pays there (Table 1 with two or more levels)
+    st, sched, lev, base, _ = capi.wsmul_autotune(16384, 16384, 16384, 1048573,
+                                                 base=capi.WS_BASE_F64_MFMA)
+    assert st == capi.WS_OK and sched == capi.WS_TWO_TEMP and lev >= 2
